@@ -1,0 +1,222 @@
+"""Seeded problem families shaped like the paper's workloads.
+
+Every generator draws from numpy.random.default_rng(seed) (PCG64), coefficients
+in graded monomial order, and returns a ConicProblem.
+
+* pop_unconstrained  - max gamma s.t. p - gamma SOS (Section II-B, the POP relaxation).
+* pop_ball           - Lasserre relaxation on the unit ball with a weighted SOS
+                       multiplier: p - gamma = s0 + s1 (1 - |x|^2) (Section II-B,
+                       constrained POP; Section VI, weighted SOS).
+* example_pop        - the quartic test POP of Section VII-A on the unit ball.
+* lyapunov           - global Lyapunov search for a cubic vector field
+                       (Section II-B, the Lyapunov SOS program) with a quartic V.
+* small closed forms - univariate, bivariate, separable, infeasible and unbounded
+                       programs whose answers are known without any solver.
+"""
+from __future__ import annotations
+
+from math import comb
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from .poly import Poly, monomials
+from .sdp import ConicProblem, SOSEquation, build_sos_sdp
+
+
+# ---------------------------------------------------------------- helpers
+def _sum_sq(n: int, scale: float = 1.0) -> Poly:
+    p = Poly(n)
+    for i in range(n):
+        p = p + Poly.var(n, i, 2).scale(scale)
+    return p
+
+
+def pop_from_poly(p: Poly, half_degree: int, meta: Optional[dict] = None) -> ConicProblem:
+    """max gamma s.t. p - gamma in Sigma[x]_{n,2d}; cost -gamma on the single free variable."""
+    n = p.n
+    eq = SOSEquation(row_degree=2 * half_degree, g0=p, g={0: Poly.const(n, 1.0)},
+                     blocks=[(half_degree, Poly.const(n, 1.0))])
+    md = {"kind": "pop", "gamma_index": 0, "n_vars": n, "half_degree": half_degree}
+    md.update(meta or {})
+    return build_sos_sdp(n, 1, [-1.0], [eq], md)
+
+
+def ball_pop_from_poly(p: Poly, half_degree: int, meta: Optional[dict] = None) -> ConicProblem:
+    """max gamma s.t. p - gamma = s0 + s1 (1 - |x|^2); s0 of degree 2d, s1 of degree 2d-2."""
+    n = p.n
+    ball = Poly.const(n, 1.0) - _sum_sq(n)
+    eq = SOSEquation(row_degree=2 * half_degree, g0=p, g={0: Poly.const(n, 1.0)},
+                     blocks=[(half_degree, Poly.const(n, 1.0)), (half_degree - 1, ball)])
+    md = {"kind": "ball_pop", "gamma_index": 0, "n_vars": n, "half_degree": half_degree}
+    md.update(meta or {})
+    return build_sos_sdp(n, 1, [-1.0], [eq], md)
+
+
+# ---------------------------------------------------------------- quartic POPs
+def quartic_poly(n: int, rng: np.random.Generator, cross_std: float = 0.0) -> Poly:
+    """sum_i x_i^4 + N(0,1) on every monomial of degree <= 3 (+ N(0,cross_std) on quartic cross terms)."""
+    terms = {}
+    low = monomials(n, 3)
+    coef = rng.standard_normal(len(low))
+    for e, c in zip(low, coef):
+        terms[e] = c
+    if cross_std > 0.0:
+        quart = [e for e in monomials(n, 4, min_degree=4) if max(e) < 4]
+        cc = rng.standard_normal(len(quart)) * cross_std
+        for e, c in zip(quart, cc):
+            terms[e] = c
+    for i in range(n):
+        e = [0] * n
+        e[i] = 4
+        terms[tuple(e)] = 1.0
+    return Poly(n, terms)
+
+
+def pop_unconstrained(n: int, seed: int, cross_std: float = 0.0) -> ConicProblem:
+    """Unconstrained quartic POP relaxation (one Gram block of size C(n+2,2))."""
+    rng = np.random.default_rng(seed)
+    p = quartic_poly(n, rng, cross_std)
+    return pop_from_poly(p, 2, {"family": "pop_unconstrained", "seed": seed, "cross_std": cross_std})
+
+
+def pop_batch_member(seed: int) -> ConicProblem:
+    """Batch member: n ~ U{6..16} drawn first from the seed's stream, then the quartic POP at that n."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(6, 17))
+    p = quartic_poly(n, rng, 0.0)
+    return pop_from_poly(p, 2, {"family": "pop_batch", "seed": seed})
+
+
+def pop_ball(n: int, seed: int) -> ConicProblem:
+    """Quartic POP on the unit ball, N(0,1) on every monomial of degree <= 4, weighted multiplier."""
+    rng = np.random.default_rng(seed)
+    mons = monomials(n, 4)
+    coef = rng.standard_normal(len(mons))
+    p = Poly(n, dict(zip(mons, coef)))
+    return ball_pop_from_poly(p, 2, {"family": "pop_ball", "seed": seed})
+
+
+def example_pop_poly(n: int) -> Poly:
+    """sum_{i<j} (x_i x_j + x_i^2 x_j - x_j^3 - x_i^2 x_j^2)  (Section VII-A test polynomial)."""
+    p = Poly(n)
+    for j in range(n):
+        for i in range(j):
+            xi, xj = Poly.var(n, i), Poly.var(n, j)
+            p = p + xi * xj + Poly.var(n, i, 2) * xj - Poly.var(n, j, 3) - Poly.var(n, i, 2) * Poly.var(n, j, 2)
+    return p
+
+
+def example_pop(n: int) -> ConicProblem:
+    """Order-2 (2d = 4) Lasserre relaxation of the Section VII-A POP on the unit ball."""
+    return ball_pop_from_poly(example_pop_poly(n), 2, {"family": "example_pop"})
+
+
+# ---------------------------------------------------------------- Lyapunov family
+def lyapunov_field(n: int, rng: np.random.Generator):
+    """f_i = -x_i - x_i^3 + sigma * sum_alpha c_{i,alpha} x^alpha over all quadratic monomials."""
+    sigma = float(rng.uniform(0.0, 0.5))
+    quad = monomials(n, 2, min_degree=2)
+    coef = rng.standard_normal((n, len(quad)))
+    f = []
+    for i in range(n):
+        fi = -Poly.var(n, i) - Poly.var(n, i, 3)
+        for e, c in zip(quad, coef[i]):
+            fi = fi + Poly.mono(e, sigma * c)
+        f.append(fi)
+    return sigma, coef, f
+
+
+def lyapunov_from_field(n: int, f: Sequence[Poly], eps: float = 1.0, meta: Optional[dict] = None) -> ConicProblem:
+    """find V = sum_i u_i x^{a_i} (2 <= |a_i| <= 4) with V - eps|x|^2 SOS and -grad V . f - eps|x|^2 SOS."""
+    vmons = monomials(n, 4, min_degree=2)
+    t = len(vmons)
+    neg_sq = -_sum_sq(n, eps)
+    g1 = {i: Poly.mono(e, -1.0) for i, e in enumerate(vmons)}
+    g2 = {}
+    for i, e in enumerate(vmons):
+        mono = Poly.mono(e)
+        acc = Poly(n)
+        for k in range(n):
+            acc = acc + mono.diff(k) * f[k]
+        g2[i] = acc
+    eq1 = SOSEquation(row_degree=4, g0=neg_sq, g=g1, blocks=[(2, Poly.const(n, 1.0))])
+    eq2 = SOSEquation(row_degree=6, g0=neg_sq, g=g2, blocks=[(3, Poly.const(n, 1.0))])
+    md = {"kind": "lyapunov", "n_vars": n, "eps": eps, "v_monomials": t}
+    md.update(meta or {})
+    return build_sos_sdp(n, t, np.zeros(t), [eq1, eq2], md)
+
+
+def lyapunov(seed: int, n: int = 6, eps: float = 1.0) -> ConicProblem:
+    rng = np.random.default_rng(seed)
+    sigma, coef, f = lyapunov_field(n, rng)
+    features = np.concatenate([[sigma], (sigma * coef).reshape(-1)])
+    return lyapunov_from_field(n, f, eps, {"family": "lyapunov", "seed": seed, "sigma": sigma,
+                                           "features": features})
+
+
+def lyapunov_features(seed: int, n: int = 6) -> np.ndarray:
+    """The warm-start model's input for one instance: [sigma, sigma * c_{i,alpha}] (1 + n * C(n+1,2))."""
+    rng = np.random.default_rng(seed)
+    sigma = float(rng.uniform(0.0, 0.5))
+    quad = monomials(n, 2, min_degree=2)
+    coef = rng.standard_normal((n, len(quad)))
+    return np.concatenate([[sigma], (sigma * coef).reshape(-1)])
+
+
+# ---------------------------------------------------------------- closed-form cases
+def univariate(coeffs_low_to_high: Sequence[float]) -> ConicProblem:
+    """max gamma s.t. p - gamma SOS for p(x) = sum_k a_k x^k of even degree."""
+    deg = len(coeffs_low_to_high) - 1
+    if deg % 2:
+        raise ValueError("even degree required")
+    p = Poly(1, {(k,): float(a) for k, a in enumerate(coeffs_low_to_high)})
+    return pop_from_poly(p, deg // 2, {"family": "univariate"})
+
+
+def bivariate_quartic(seed: int) -> ConicProblem:
+    """x^4 + y^4 + N(0,1) on every monomial of degree <= 3 in two variables."""
+    rng = np.random.default_rng(seed)
+    return pop_from_poly(quartic_poly(2, rng, 0.0), 2, {"family": "bivariate", "seed": seed})
+
+
+def separable_quartic(n: int, seed: int):
+    """p = sum_i q_i(x_i) with q_i = x^4 + a3 x^3 + a2 x^2 + a1 x; returns (problem, list of q_i coeffs)."""
+    rng = np.random.default_rng(seed)
+    qs = []
+    terms = {}
+    for i in range(n):
+        a = rng.standard_normal(3)
+        qs.append(np.array([0.0, a[0], a[1], a[2], 1.0]))
+        for k, ak in zip((1, 2, 3, 4), (a[0], a[1], a[2], 1.0)):
+            e = [0] * n
+            e[i] = k
+            terms[tuple(e)] = ak
+    return pop_from_poly(Poly(n, terms), 2, {"family": "separable", "seed": seed}), qs
+
+
+def infeasible_pop() -> ConicProblem:
+    """max gamma s.t. -x^2 - gamma SOS: no Gram matrix can match a negative x^2 coefficient."""
+    return pop_from_poly(Poly(1, {(2,): -1.0}), 1, {"family": "infeasible"})
+
+
+def unbounded_pop() -> ConicProblem:
+    """min gamma s.t. x^2 - gamma SOS (cost +gamma): gamma can go to -infinity."""
+    p = Poly(1, {(2,): 1.0})
+    eq = SOSEquation(row_degree=2, g0=p, g={0: Poly.const(1, 1.0)}, blocks=[(1, Poly.const(1, 1.0))])
+    return build_sos_sdp(1, 1, [1.0], [eq], {"family": "unbounded", "gamma_index": 0})
+
+
+def shape_counts(n: int, two_d: int):
+    """(N, m) = (C(n+d, d), C(n+2d, 2d)) for the full monomial basis (Section II-C)."""
+    d = two_d // 2
+    return comb(n + d, d), comb(n + two_d, two_d)
+
+
+FAMILIES = {
+    "c1": lambda seed=0: pop_unconstrained(4, seed),
+    "c2": lambda seed=0: pop_unconstrained(20, seed, cross_std=0.1),
+    "c3": lambda seed=0: pop_ball(16, seed),
+    "c4": pop_batch_member,
+    "c5": lyapunov,
+}

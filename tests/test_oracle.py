@@ -1,0 +1,280 @@
+"""Pins for the CPU oracle, each against something other than the oracle itself.
+
+* the affine step against a dense LU of the whole (I + Q) (brute force);
+* the PSD projection against (W + |W|)/2 with |W| from a matrix square root, and
+  against the Moreau decomposition;
+* iteration invariants that the three ADMM steps of Section IV-A imply;
+* whole solves against closed forms and brute-force minima;
+* planted mistakes in a copy of the oracle, which these pins must catch.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle.admm import (DUAL_INFEASIBLE, PRIMAL_INFEASIBLE, SOLVED, Oracle, proj_psd)
+from sosgen import Poly, families as F
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table3_example_pop.json")))
+
+
+def dense_IQ(o: Oracle) -> np.ndarray:
+    """I + Q assembled entry by entry from its block definition (Section IV-A)."""
+    n, m = o.n, o.m
+    A = o.A.toarray()
+    K = n + m + 1
+    Q = np.zeros((K, K))
+    Q[:n, n:n + m] = -A.T
+    Q[:n, -1] = o.c
+    Q[n:n + m, :n] = A
+    Q[n:n + m, -1] = -o.b
+    Q[-1, :n] = -o.c
+    Q[-1, n:n + m] = o.b
+    return np.eye(K) + Q
+
+
+SMALL = {
+    "c1": lambda: F.FAMILIES["c1"](0),
+    "ball2": lambda: F.pop_ball(2, 1),
+    "lyap2": lambda: F.lyapunov_from_field(2, F.lyapunov_field(2, np.random.default_rng(4))[2]),
+    "univ": lambda: F.univariate([0.3, -1.0, 0.2, 0.5, 1.0]),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_affine_step_matches_dense_LU(name):
+    o = Oracle.from_problem(SMALL[name]())
+    M = dense_IQ(o)
+    assert np.allclose(M - np.eye(len(M)), -(M - np.eye(len(M))).T)     # Q is skew-symmetric
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        w = rng.standard_normal(len(M))
+        ref = sla.lu_solve(sla.lu_factor(M), w)
+        got = o.affine(w)
+        assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+        assert np.linalg.norm(M @ got - w) <= 1e-10 * np.linalg.norm(w)
+
+
+def test_Q_matvec_is_skew_operator():
+    o = Oracle.from_problem(SMALL["c1"]())
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(o.n + o.m + 1)
+    assert abs(x @ o.Q_matvec(x)) < 1e-10 * (x @ x)
+    assert np.allclose(o.Q_matvec(x), (dense_IQ(o) - np.eye(len(x))) @ x)
+
+
+def test_projection_pins():
+    rng = np.random.default_rng(2)
+    assert np.allclose(proj_psd(np.array([[-2.5]])), 0.0)
+    assert np.allclose(proj_psd(np.array([[1.5]])), 1.5)
+    for N in (2, 5, 17):
+        R = rng.standard_normal((N, N))
+        W = R + R.T
+        P = proj_psd(W)
+        Pm = proj_psd(-W)
+        # (W + |W|)/2 with |W| = sqrtm(W^2): an independent route to P_{S+}(W)
+        absW = np.real(sla.sqrtm(W @ W))
+        assert np.allclose(P, 0.5 * (W + absW), atol=1e-9)
+        # Moreau: W = P(W) - P(-W), <P(W), P(-W)> = 0, both PSD
+        assert np.allclose(P - Pm, W, atol=1e-10)
+        assert abs(np.sum(P * Pm)) < 1e-9
+        assert np.linalg.eigvalsh(P).min() > -1e-10 and np.linalg.eigvalsh(Pm).min() > -1e-10
+        # distance optimality against random PSD points
+        for _ in range(5):
+            S = rng.standard_normal((N, N))
+            S = S @ S.T
+            assert np.linalg.norm(W - P) <= np.linalg.norm(W - S) + 1e-12
+
+
+@pytest.mark.parametrize("name", ["c1", "ball2", "lyap2"])
+def test_iteration_invariants(name):
+    # u in C, v in C*, u . v = 0, v_y = 0, v_free = 0 after every step (Section IV-A plus Moreau)
+    o = Oracle.from_problem(SMALL[name]())
+    u, v = o.initial()
+    n, m = o.n, o.m
+    for k in range(25):
+        u, v = o.step(u, v)
+        scale = 1 + np.linalg.norm(u) + np.linalg.norm(v)
+        assert abs(u @ v) <= 1e-10 * scale ** 2
+        assert np.all(v[n:n + m] == 0.0)
+        assert np.all(v[:o.n_free] == 0.0)
+        assert u[-1] >= 0 and v[-1] >= 0 and u[-1] * v[-1] == 0.0
+        off = o.n_free
+        for N in o.psd_dims:
+            for vec in (u, v):
+                B = vec[off:off + N * N].reshape(N, N, order="F")
+                assert np.allclose(B, B.T, atol=1e-12 * scale)
+                assert np.linalg.eigvalsh(B).min() >= -1e-9 * scale
+            off += N * N
+
+
+def test_fixed_point_of_solution():
+    # a solution of the embedding with tau = 1, kappa = 0 is a fixed point of the iteration
+    o = Oracle.from_problem(F.univariate([1.0, 0.0, -2.0, 0.0, 1.0]))
+    r = o.solve(tol=1e-10, max_iters=20000)
+    n, m = o.n, o.m
+    u = np.concatenate([r.x, r.y, [1.0]])
+    v = np.concatenate([r.z, np.zeros(m), [0.0]])
+    u2, v2 = o.step(u, v)
+    assert np.linalg.norm(u2 - u) < 1e-7 and np.linalg.norm(v2 - v) < 1e-7
+
+
+def test_closed_form_x_squared_and_double_well():
+    # x^2: gamma* = 0.  (x^2 - 1)^2: gamma* = 0 with the unique Gram matrix [[1,0,-1],[0,0,0],[-1,0,1]]
+    r = Oracle.from_problem(F.univariate([0.0, 0.0, 1.0])).solve(tol=1e-9, max_iters=20000)
+    assert r.status == SOLVED and abs(r.x[0]) < 1e-6
+    o = Oracle.from_problem(F.univariate([1.0, 0.0, -2.0, 0.0, 1.0]))
+    r = o.solve(tol=1e-9, max_iters=20000)
+    assert r.status == SOLVED and abs(r.x[0]) < 1e-6
+    X = r.x[1:].reshape(3, 3, order="F")
+    assert np.allclose(X, [[1, 0, -1], [0, 0, 0], [-1, 0, 1]], atol=1e-5)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_univariate_bound_equals_brute_force_minimum(seed):
+    # nonnegative univariate polynomials are SOS, so gamma* = min p (critical points from p')
+    rng = np.random.default_rng(100 + seed)
+    a = np.concatenate([rng.standard_normal(6), [1.0]])        # degree 6, leading coefficient 1
+    crit = np.roots(np.polyder(a[::-1]))
+    crit = crit[np.abs(crit.imag) < 1e-9].real
+    pmin = min(np.polyval(a[::-1], crit))
+    grid = np.linspace(-5, 5, 200001)
+    assert pmin <= np.polyval(a[::-1], grid).min() + 1e-12
+    r = Oracle.from_problem(F.univariate(a)).solve(tol=1e-8, max_iters=50000)
+    assert r.status == SOLVED
+    assert abs(r.x[0] - pmin) <= 1e-5 * max(1.0, abs(pmin))
+
+
+def test_separable_quartic():
+    # p = sum_i q_i(x_i): p - sum_i min q_i is a sum of nonnegative univariate terms, hence SOS
+    prob, qs = F.separable_quartic(3, 5)
+    ref = 0.0
+    for q in qs:
+        crit = np.roots(np.polyder(q[::-1]))
+        crit = crit[np.abs(crit.imag) < 1e-9].real
+        ref += min(np.polyval(q[::-1], crit))
+    r = Oracle.from_problem(prob).solve(tol=1e-8, max_iters=50000)
+    assert r.status == SOLVED and abs(r.x[0] - ref) <= 1e-5 * max(1, abs(ref))
+
+
+def _global_min(poly: Poly, n: int, ball: bool, starts):
+    from scipy.optimize import minimize
+    E = np.array([e for e, _ in poly.items()])
+    C = np.array([c for _, c in poly.items()])
+
+    def f(x):
+        return float(C @ np.prod(np.clip(x, -10, 10)[None, :] ** E, axis=1))
+
+    best = np.inf
+    for x0 in starts:
+        if ball:
+            r = minimize(f, x0, method="SLSQP", bounds=[(-1, 1)] * n,
+                         constraints=[{"type": "ineq", "fun": lambda x: 1 - x @ x, "jac": lambda x: -2 * x}],
+                         options={"maxiter": 1000, "ftol": 1e-14})
+            ok = r.x @ r.x <= 1 + 1e-9
+        else:
+            r = minimize(f, x0, method="BFGS", options={"gtol": 1e-10})
+            ok = True
+        if ok:
+            best = min(best, r.fun)
+    return best
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_bivariate_quartic_equals_global_min(seed):
+    # Hilbert: nonnegative bivariate quartics are SOS, so gamma* = global minimum
+    prob = F.bivariate_quartic(seed)
+    rng = np.random.default_rng(seed)
+    poly = F.quartic_poly(2, rng, 0.0)
+    g = np.linspace(-3, 3, 121)
+    starts = [np.array([a, b]) for a in g[::10] for b in g[::10]]
+    ref = _global_min(poly, 2, False, starts)
+    r = Oracle.from_problem(prob).solve(tol=1e-8, max_iters=50000)
+    assert r.status == SOLVED and abs(r.x[0] - ref) <= 1e-5 * max(1, abs(ref))
+
+
+def test_infeasible_and_unbounded_certificates():
+    r = Oracle.from_problem(F.infeasible_pop()).solve(tol=1e-6, max_iters=5000)
+    assert r.status == PRIMAL_INFEASIBLE
+    r = Oracle.from_problem(F.unbounded_pop()).solve(tol=1e-6, max_iters=5000)
+    assert r.status == DUAL_INFEASIBLE
+
+
+def test_lyapunov_unperturbed_is_feasible():
+    # sigma = 0: f = -x - x^3, V = |x|^2 (+ quartic terms) certifies stability
+    n = 3
+    f = [-Poly.var(n, i) - Poly.var(n, i, 3) for i in range(n)]
+    prob = F.lyapunov_from_field(n, f, eps=1.0)
+    r = Oracle.from_problem(prob).solve(tol=1e-6, max_iters=20000)
+    assert r.status == SOLVED
+
+
+@pytest.mark.parametrize("n", [4, 6, 10])
+def test_example_pop_matches_brute_force_and_table3(n):
+    # Section VII-A polynomial on the unit ball: the order-2 relaxation is tight here, so gamma*
+    # equals the brute-force minimum; Table III's interior-point value agrees to 0.25 %.
+    prob = F.example_pop(n)
+    r = Oracle.from_problem(prob).solve(tol=1e-7, max_iters=50000)
+    assert r.status == SOLVED
+    gamma = r.x[0]
+    poly = F.example_pop_poly(n)
+    starts = [s * np.eye(n)[k] for k in range(n) for s in (1, -1)]
+    ref = _global_min(poly, n, True, starts)
+    assert gamma <= ref + 1e-5                     # a relaxation bound never exceeds the minimum
+    assert abs(gamma - ref) <= 2e-5 * abs(ref)
+    assert gamma <= -(n - 1)                       # p(e_n) = -(n-1)
+    if str(n) in GOLD["ipm_gamma"]:
+        assert abs(gamma - GOLD["ipm_gamma"][str(n)]) <= 2.5e-3 * abs(gamma)
+
+
+# ---------------------------------------------------------------- planted mistakes
+class _DropTheta(Oracle):
+    def affine(self, omega):
+        n, m = self.n, self.m
+        w1, w2, w3 = omega[:n], omega[n:n + m], omega[n + m]
+        s1, s2 = self.solve_M(w1 - self.c * w3, w2 + self.b * w3)
+        u3 = w3 + self.c @ s1 - self.b @ s2
+        return np.concatenate([s1, s2, [u3]])
+
+
+class _WrongSignB(Oracle):
+    def affine(self, omega):
+        n, m = self.n, self.m
+        w1, w2, w3 = omega[:n], omega[n:n + m], omega[n + m]
+        s1, s2 = self.solve_M(w1 - self.c * w3, w2 - self.b * w3)
+        theta = (self.c @ s1 - self.b @ s2) / self.eta
+        u1, u2 = s1 - theta * self.h[:n], s2 - theta * self.h[n:]
+        return np.concatenate([u1, u2, [w3 + self.c @ u1 - self.b @ u2]])
+
+
+class _TransposedProjection(Oracle):
+    def project_K(self, x):
+        out = x.copy()
+        off = self.n_free
+        for N in self.psd_dims:
+            W = x[off:off + N * N].reshape(N, N, order="F")
+            lam, V = np.linalg.eigh(0.5 * (W + W.T))
+            out[off:off + N * N] = ((V.T * np.maximum(lam, 0)) @ V).reshape(-1, order="F")
+            off += N * N
+        return out
+
+
+@pytest.mark.parametrize("cls", [_DropTheta, _WrongSignB])
+def test_planted_affine_mistakes_are_caught(cls):
+    o = cls.from_problem(SMALL["c1"]())
+    M = dense_IQ(o)
+    w = np.random.default_rng(0).standard_normal(len(M))
+    assert np.linalg.norm(M @ o.affine(w) - w) > 1e-3 * np.linalg.norm(w)
+
+
+def test_planted_projection_mistake_is_caught():
+    o = _TransposedProjection.from_problem(F.univariate([1.0, 0.0, -2.0, 0.0, 1.0]))
+    try:
+        with np.errstate(all="ignore"):
+            r = o.solve(tol=1e-9, max_iters=3000)
+        caught = not (r.status == SOLVED and abs(r.x[0]) < 1e-6)
+    except (ValueError, np.linalg.LinAlgError):
+        caught = True                      # the iteration diverged to non-finite values
+    assert caught
