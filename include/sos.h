@@ -1,0 +1,190 @@
+/*
+ * sos.h - C ABI of the MI355X (gfx950) HSDE-ADMM solver for SOS-derived SDPs.
+ *
+ * Method: Zheng, Fantuzzi, Papachristodoulou, "Fast ADMM for sum-of-squares
+ * programs using partial orthogonality" (arXiv 1708.04174).
+ *
+ *   primal   min c^T xi  s.t.  A xi = b,  xi in K = R^{n_free} x S^{N_1}_+ x ...   (Section III)
+ *   dual     max b^T y   s.t.  A^T y + z = c,  z in K*                             (Section IV-A)
+ *   state    u = (xi, y, tau), v = (z, s, kappa) of the homogeneous self-dual
+ *            embedding v = Q u (Section IV-A); one iteration = the affine solve
+ *            with I + Q, the projection onto C = K x R^m x R_+, and the dual
+ *            update (the three ADMM steps of Section IV-A).
+ *   affine   I + A A^T = P + A_f A_f^T with P diagonal (Proposition 1 and its
+ *            weighted form in Section VI); solved with the matrix inversion lemma
+ *            and a cached FP64 Cholesky of I + A_f^T P^{-1} A_f (Section IV-B).
+ *
+ * Conventions for every function below
+ *   - Return value: SOS_OK (0) or a negative SOS_E_* code.  Nothing throws across
+ *     the ABI.  sos_last_error() gives a message for the last failure on a handle.
+ *   - Host arrays passed in are read during the call only (the caller keeps
+ *     ownership and may free them on return).  Output arrays are caller-owned
+ *     host arrays of the documented length.
+ *   - The library allocates and owns its device memory (HIP).  All device work of
+ *     a handle is ordered on the hipStream_t given to sos_setup (NULL = the
+ *     default stream).  A handle is not thread-safe.
+ *   - Layout at the ABI is the paper's: every PSD block is the column-stacked vec
+ *     of its N x N matrix (Section III).  Columns (i,j) and (j,i) of a PSD block
+ *     must be identical (coefficient matching always produces this, since the
+ *     indicator matrices are symmetric).  Internally the library keeps the lower
+ *     triangle of every block (unscaled) and weighs off-diagonal entries by 2 in
+ *     inner products, so its iterates are exactly the lower triangles of the
+ *     full-vec iterates and conversion at the ABI is a copy.
+ */
+#ifndef SOS_H
+#define SOS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define SOS_OK        0
+#define SOS_E_INVAL  (-1)   /* bad dimensions, bad CSC structure, non-finite data, bad settings */
+#define SOS_E_ASYM   (-2)   /* a PSD block's columns (i,j) and (j,i), or its cost, differ */
+#define SOS_E_NOMEM  (-3)   /* host or device allocation failed */
+#define SOS_E_HIP    (-4)   /* a HIP runtime call failed (no device, launch failure, ...) */
+#define SOS_E_STATE  (-5)   /* call not valid in the handle's current state */
+
+/* solve status (a status, never an error) */
+#define SOS_UNSOLVED           0
+#define SOS_SOLVED             1   /* max(res_pri, res_dual, gap) <= tol */
+#define SOS_PRIMAL_INFEASIBLE  2   /* b^T y > 0 and |A^T y + z| <= tol b^T y  (tau -> 0 certificate) */
+#define SOS_DUAL_INFEASIBLE    3   /* c^T xi < 0 and |A xi| <= tol (-c^T xi) */
+#define SOS_MAX_ITERS          4
+
+/* precision forms */
+#define SOS_FP64        0   /* every step in FP64 */
+#define SOS_FP32_MIXED  1   /* FP32 bulk (matvecs, eigensolves, FP32 accumulation); FP64 for the
+                               Cholesky solve, theta, tau/kappa, residuals; FP64 polish at the end */
+
+/* column partition of A into the diagonal part A_s and the low-rank part A_f */
+#define SOS_PART_PAPER    0  /* A_f = all free columns + every PSD column with >= 2 nonzeros (Sections IV-B, VI) */
+#define SOS_PART_COLUMNS  1  /* A_f = only columns with >= 2 nonzeros (any column with one nonzero keeps P diagonal) */
+
+typedef struct sos_work  sos_work;
+typedef struct sos_batch sos_batch;
+
+/* Host CSC matrix, m rows, n = n_free + sum_j N_j^2 columns; rowind sorted within a column. */
+typedef struct {
+    int32_t m, n;
+    const int64_t *colptr;   /* n + 1 entries, colptr[0] = 0 */
+    const int32_t *rowind;   /* colptr[n] entries, 0 <= rowind < m */
+    const double  *val;      /* colptr[n] entries, finite */
+} sos_csc;
+
+/* Cone K = R^{n_free} x S^{N[0]}_+ x ... x S^{N[n_psd-1]}_+ */
+typedef struct {
+    int32_t n_free;
+    int32_t n_psd;
+    const int32_t *N;        /* n_psd block sizes, each >= 1 */
+} sos_cone;
+
+typedef struct {
+    double  tol;             /* stop when max(res_pri, res_dual, gap) <= tol, or on a certificate */
+    int32_t max_iters;
+    int32_t check_every;     /* residuals (FP64) are evaluated every check_every iterations */
+    double  alpha;           /* relaxation; 1.0 = the paper's three steps unchanged */
+    int32_t precision;       /* SOS_FP64 | SOS_FP32_MIXED */
+    int32_t polish_iters;    /* FP64 iterations after an FP32 solve (>= 1 for SOS_FP32_MIXED) */
+    int32_t partition;       /* SOS_PART_PAPER | SOS_PART_COLUMNS */
+    int32_t block_threads;   /* threads per workgroup: 0 = default (256), else 64..1024, multiple of 64 */
+} sos_settings;
+
+typedef struct {
+    int32_t status;          /* SOS_* status above */
+    int32_t iters;           /* total iterations run (FP32 + FP64 polish) */
+    int32_t k_lowrank;       /* columns of A_f = size of the cached Cholesky factor */
+    int32_t polish_iters;    /* FP64 iterations run after the FP32 phase */
+    double  pobj, dobj;      /* c^T xi / tau, b^T y / tau */
+    double  res_pri, res_dual, gap;   /* |A xi - b tau|/tau/(1+|b|), |A^T y + z - c tau|/tau/(1+|c|),
+                                         |c^T xi - b^T y|/tau/(1 + |c^T xi|/tau + |b^T y|/tau), FP64 */
+    double  tau, kappa;
+    double  setup_ms, solve_ms;
+} sos_info;
+
+/* Fills *s with tol 1e-4, max_iters 2000, check_every 10, alpha 1, SOS_FP64,
+   polish_iters 1, SOS_PART_PAPER, block_threads 0.  Returns SOS_E_INVAL if s is NULL. */
+int sos_default_settings(sos_settings *s);
+
+/* Validates the problem, folds PSD blocks to their lower triangles, splits A = [A_f A_s]
+   (Proposition 1; Section VI for weighted blocks), forms d = 1 + diag(A_s A_s^T),
+   S = I + A_f^T D^{-1} A_f (written over lower-triangle columns: W_f^{-1} + ...,
+   W_f the weights 1 / 2) and its FP64 Cholesky factor, h = M^{-1} zeta and
+   eta = 1 + zeta^T h with zeta = (c, -b) (Section IV-B), uploads everything to the
+   current HIP device, and sets the cold start u = v = (0, 0, 1).
+   A, b (m), c (n), K, s: host inputs.  s may be NULL (defaults).  hip_stream: a
+   hipStream_t or NULL.  *out receives the new handle (NULL on failure).
+   Errors: SOS_E_INVAL, SOS_E_ASYM, SOS_E_NOMEM, SOS_E_HIP. */
+int sos_setup(const sos_csc *A, const double *b, const double *c, const sos_cone *K,
+              const sos_settings *s, void *hip_stream, sos_work **out);
+
+/* Runs exactly `iters` ADMM iterations from the current state, in the handle's
+   precision, with no early stop; then evaluates the FP64 residuals once and fills
+   *info (status SOS_UNSOLVED unless a stopping test already holds).  Blocks until
+   the stream has finished.  iters >= 0.  info may be NULL. */
+int sos_step(sos_work *w, int32_t iters, sos_info *info);
+
+/* Iterates from the current state until a stopping test holds or max_iters; in
+   SOS_FP32_MIXED form the FP32 phase is followed by FP64 iterations (at least
+   polish_iters) until the FP64 residuals meet tol.  Blocks until done. */
+int sos_solve(sos_work *w, sos_info *info);
+
+/* Sets u = (tau x, tau y, tau), v = (tau z, 0, kappa).  x, z: n entries (full vec,
+   PSD blocks symmetric), y: m entries.  z must be zero on the free part (K* there
+   is {0}).  tau >= 0, kappa >= 0, not both zero. */
+int sos_warm_start(sos_work *w, const double *x, const double *y, const double *z,
+                   double tau, double kappa);
+
+/* Copies xi/tau, y/tau, z/tau (full vec) into x (n), y (m), z (n).  Any pointer
+   may be NULL to skip it.  SOS_E_STATE if tau == 0 (use sos_get_iterate). */
+int sos_get_solution(const sos_work *w, double *x, double *y, double *z);
+
+/* Raw embedding state: u = (xi, y, tau), v = (z, s, kappa), each n + m + 1 entries. */
+int sos_get_iterate(const sos_work *w, double *u, double *v);
+
+/* Restores a state taken with sos_get_iterate (checkpoint / resume).  The s part
+   of v and the free part of z must be zero, as every iterate of the method has. */
+int sos_set_iterate(sos_work *w, const double *u, const double *v);
+
+/* Message for the last error on w (or on the last failed sos_setup when w is NULL). */
+const char *sos_last_error(const sos_work *w);
+
+/* Releases the handle and its device memory.  NULL is ignored. */
+void sos_free(sos_work *w);
+
+/* Groups `count` handles (same precision) for one persistent launch: workgroups
+   pull problems from a device queue ordered by decreasing cost.  schedule_json
+   (may be NULL) holds the tuned launch shape, e.g.
+   {"block_threads": 256, "wg_per_cu": 2, "max_sweeps": 60, "use_graph": 1}.
+   The handles must outlive the batch. */
+int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_json,
+                    sos_batch **out);
+
+/* Solves every problem of the batch from its current state (one captured HIP
+   graph: FP32 or FP64 persistent solve, then the FP64 polish for the mixed form).
+   infos: count entries, in the order given to sos_batch_setup. */
+int sos_batch_solve(sos_batch *b, sos_info *infos);
+
+/* Resets every problem of the batch to the cold start u = v = (0, 0, 1) with one
+   device kernel (e.g. between repeated solves of the same batch). */
+int sos_batch_reset(sos_batch *b);
+
+/* Device time in ms of the last sos_batch_solve: whole graph (hip events on the
+   batch's stream around it). */
+double sos_batch_last_ms(const sos_batch *b);
+
+/* Device time in ms of one kernel of the last sos_batch_solve, from hip events
+   recorded right around it: phase 0 = the persistent solve kernel (FP32 in the
+   mixed form), phase 1 = the FP64 polish kernel (0 for an FP64 batch).  Returns a
+   negative value if unavailable. */
+double sos_batch_phase_ms(const sos_batch *b, int32_t phase);
+
+void sos_batch_free(sos_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SOS_H */

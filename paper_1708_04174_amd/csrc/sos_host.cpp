@@ -1,0 +1,977 @@
+// Host side of the C ABI declared in include/sos.h: validation, the fold from the
+// paper's column-stacked vec to the weighted lower triangle, the A_f / A_s split, the cached
+// factor of I + A_f^T D^{-1} A_f (Section IV-B), h = M^{-1} zeta, device upload,
+// and the launches of the persistent solver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sos.h"
+#include "sos_internal.h"
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+struct DeviceArena {
+    std::vector<void *> ptrs;
+    ~DeviceArena() { release(); }
+    void release() {
+        for (void *p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+    }
+    template <typename T>
+    T *alloc(size_t n) {
+        void *p = nullptr;
+        size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return static_cast<T *>(p);
+    }
+};
+
+int svec_index(int i, int j, int N) {   // i >= j, lower triangle by columns
+    return j * N - (j * (j - 1)) / 2 + (i - j);
+}
+
+struct Status : std::exception {
+    int code;
+    std::string msg;
+    Status(int c, std::string m) : code(c), msg(std::move(m)) {}
+};
+
+void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) throw Status(SOS_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+void upload(T *dst, const std::vector<T> &src, hipStream_t st) {
+    if (!src.empty()) hip_check(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st),
+                                "hipMemcpyAsync");
+}
+
+template <typename T>
+std::vector<float> to_f32(const std::vector<T> &x) {
+    std::vector<float> y(x.size());
+    for (size_t i = 0; i < x.size(); ++i) y[i] = (float)x[i];
+    return y;
+}
+
+}   // namespace
+
+struct sos_work {
+    sos_settings st{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    int m = 0, n_full = 0, nx = 0, nfree = 0, k = 0;
+    std::vector<int> N, off_full, off_svec;
+    int nmax = 0;
+    DeviceArena mem;
+    ProbDesc desc{};          // host copy
+    ProbDesc *d_desc = nullptr;
+    int *d_counter = nullptr, *d_order = nullptr;
+    void *d_work = nullptr, *d_eig = nullptr;
+    long long work_stride = 0, eig_stride = 0;
+    int eig_ld = 0;
+    int threads = 256;
+    bool active64 = true;     // which copy of (u, v) holds the current iterate
+    double setup_ms = 0.0, last_ms = 0.0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+struct sos_batch {
+    std::vector<sos_work *> probs;
+    DeviceArena mem;
+    ProbDesc *d_desc = nullptr;
+    int *d_order = nullptr, *d_counter = nullptr;
+    double *d_out = nullptr;
+    void *d_work = nullptr, *d_eig = nullptr;
+    long long work_stride = 0, eig_stride = 0;
+    int eig_ld = 0, threads = 256, grid = 1, count = 0, fp64 = 1, wg_per_cu = 2, max_sweeps = 40;
+    int max_len = 0;
+    hipStream_t stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t evp[4] = {nullptr, nullptr, nullptr, nullptr};   // around the solve and polish kernels
+    double last_ms = 0.0, phase_ms[2] = {0.0, 0.0};
+    bool use_graph = true;
+    sos_settings st{};
+};
+
+namespace {
+
+void default_settings(sos_settings *s) {
+    s->tol = 1e-4;
+    s->max_iters = 2000;
+    s->check_every = 10;
+    s->alpha = 1.0;
+    s->precision = SOS_FP64;
+    s->polish_iters = 1;
+    s->partition = SOS_PART_PAPER;
+    s->block_threads = 0;
+}
+
+void check_settings(const sos_settings &s) {
+    if (!(s.tol > 0.0) || s.max_iters < 0 || s.check_every < 1 || !(s.alpha > 0.0 && s.alpha < 2.0))
+        throw Status(SOS_E_INVAL, "invalid settings (tol > 0, max_iters >= 0, check_every >= 1, 0 < alpha < 2)");
+    if (s.precision != SOS_FP64 && s.precision != SOS_FP32_MIXED) throw Status(SOS_E_INVAL, "invalid precision");
+    if (s.partition != SOS_PART_PAPER && s.partition != SOS_PART_COLUMNS) throw Status(SOS_E_INVAL, "invalid partition");
+    if (s.block_threads != 0 && (s.block_threads < 64 || s.block_threads > 1024 || (s.block_threads & (s.block_threads - 1))))
+        throw Status(SOS_E_INVAL, "block_threads must be 0 or a power of two in 64..1024");
+    if (s.precision == SOS_FP32_MIXED && s.polish_iters < 1) throw Status(SOS_E_INVAL, "polish_iters >= 1 required");
+}
+
+// Dense Cholesky of the k x k SPD matrix S (row-major), lower factor in place.
+void cholesky(std::vector<double> &S, int k) {
+    for (int j = 0; j < k; ++j) {
+        double d = S[(size_t)j * k + j];
+        for (int p = 0; p < j; ++p) d -= S[(size_t)j * k + p] * S[(size_t)j * k + p];
+        if (!(d > 0.0)) throw Status(SOS_E_INVAL, "I + A_f^T D^{-1} A_f is not positive definite");
+        const double ljj = std::sqrt(d);
+        S[(size_t)j * k + j] = ljj;
+        for (int i = j + 1; i < k; ++i) {
+            double s = S[(size_t)i * k + j];
+            for (int p = 0; p < j; ++p) s -= S[(size_t)i * k + p] * S[(size_t)j * k + p];
+            S[(size_t)i * k + j] = s / ljj;
+        }
+    }
+}
+
+void build(sos_work *w, const sos_csc *A, const double *b, const double *c, const sos_cone *K) {
+    if (!A || !b || !c || !K || !A->colptr || (!A->rowind && A->colptr[A->n] > 0))
+        throw Status(SOS_E_INVAL, "null argument");
+    const int m = A->m, n = A->n;
+    if (m < 0 || n < 1 || K->n_free < 0 || K->n_psd < 0 || K->n_psd > SOS_MAX_BLOCKS)
+        throw Status(SOS_E_INVAL, "bad dimensions (at most 8 PSD blocks)");
+    long long ncheck = K->n_free;
+    for (int j = 0; j < K->n_psd; ++j) {
+        if (K->N[j] < 1 || K->N[j] > 2048) throw Status(SOS_E_INVAL, "PSD block size must be in 1..2048");
+        ncheck += (long long)K->N[j] * K->N[j];
+    }
+    if (ncheck != n) throw Status(SOS_E_INVAL, "A has n != n_free + sum N_j^2 columns");
+    if (A->colptr[0] != 0) throw Status(SOS_E_INVAL, "colptr[0] != 0");
+    for (int j = 0; j < n; ++j) {
+        if (A->colptr[j + 1] < A->colptr[j]) throw Status(SOS_E_INVAL, "colptr not monotone");
+        for (long long e = A->colptr[j]; e < A->colptr[j + 1]; ++e) {
+            const int r = A->rowind[e];
+            if (r < 0 || r >= m) throw Status(SOS_E_INVAL, "row index out of range");
+            if (e > A->colptr[j] && A->rowind[e - 1] >= r) throw Status(SOS_E_INVAL, "row indices not sorted/unique");
+            if (!std::isfinite(A->val[e])) throw Status(SOS_E_INVAL, "non-finite value in A");
+        }
+    }
+    for (int i = 0; i < m; ++i)
+        if (!std::isfinite(b[i])) throw Status(SOS_E_INVAL, "non-finite b");
+    for (int j = 0; j < n; ++j)
+        if (!std::isfinite(c[j])) throw Status(SOS_E_INVAL, "non-finite c");
+
+    w->m = m;
+    w->n_full = n;
+    w->nfree = K->n_free;
+    w->N.assign(K->N, K->N + K->n_psd);
+    w->nmax = 0;
+    // symmetric column pairs, offsets
+    int off = K->n_free, soff = K->n_free;
+    for (int bk = 0; bk < K->n_psd; ++bk) {
+        const int N = K->N[bk];
+        w->off_full.push_back(off);
+        w->off_svec.push_back(soff);
+        w->nmax = std::max(w->nmax, N);
+        for (int j = 0; j < N; ++j)
+            for (int i = j + 1; i < N; ++i) {
+                const int c1 = off + j * N + i, c2 = off + i * N + j;
+                const long long l1 = A->colptr[c1 + 1] - A->colptr[c1], l2 = A->colptr[c2 + 1] - A->colptr[c2];
+                if (l1 != l2 || c[c1] != c[c2]) throw Status(SOS_E_ASYM, "PSD block columns (i,j) and (j,i) differ");
+                for (long long t = 0; t < l1; ++t)
+                    if (A->rowind[A->colptr[c1] + t] != A->rowind[A->colptr[c2] + t] ||
+                        A->val[A->colptr[c1] + t] != A->val[A->colptr[c2] + t])
+                        throw Status(SOS_E_ASYM, "PSD block columns (i,j) and (j,i) differ");
+            }
+        off += N * N;
+        soff += N * (N + 1) / 2;
+    }
+    const int nx = soff;
+    w->nx = nx;
+
+    // fold to the lower triangle: column e -> source column (i,j), i >= j; an off-diagonal
+    // entry stands for both (i,j) and (j,i) of the full vec, hence weight 2
+    std::vector<int> src_col(nx);
+    std::vector<double> wgt(nx, 1.0);
+    for (int e = 0; e < K->n_free; ++e) src_col[e] = e;
+    for (int bk = 0; bk < K->n_psd; ++bk) {
+        const int N = K->N[bk];
+        for (int j = 0; j < N; ++j)
+            for (int i = j; i < N; ++i) {
+                const int e = w->off_svec[bk] + svec_index(i, j, N);
+                src_col[e] = w->off_full[bk] + j * N + i;
+                wgt[e] = (i == j) ? 1.0 : 2.0;
+            }
+    }
+    std::vector<int> cnt(nx);
+    std::vector<double> cs(nx), cw(nx);
+    for (int e = 0; e < nx; ++e) {
+        cnt[e] = (int)(A->colptr[src_col[e] + 1] - A->colptr[src_col[e]]);
+        cs[e] = c[src_col[e]];
+        cw[e] = cs[e] * wgt[e];
+    }
+    // partition
+    std::vector<int> colrow(nx, -1), fcolof(nx, -1);
+    std::vector<int> fcols;
+    for (int e = 0; e < nx; ++e) {
+        const bool lowrank = cnt[e] >= 2 || (w->st.partition == SOS_PART_PAPER && e < K->n_free);
+        if (lowrank) {
+            fcolof[e] = (int)fcols.size();
+            colrow[e] = -2 - (int)fcols.size();
+            fcols.push_back(e);
+        }
+    }
+    const int k = (int)fcols.size();
+    if (k > SOS_KMAX_LDS) throw Status(SOS_E_INVAL, "low-rank part wider than 1024 columns is not supported");
+    w->k = k;
+    std::vector<double> colval(nx, 0.0), d(m, 1.0);
+    for (int e = 0; e < nx; ++e) {
+        if (colrow[e] <= -2) continue;
+        if (cnt[e] == 1) {
+            const long long p = A->colptr[src_col[e]];
+            colrow[e] = A->rowind[p];
+            colval[e] = A->val[p];
+            d[colrow[e]] += wgt[e] * colval[e] * colval[e];
+        }
+    }
+    // CSR of the whole svec A
+    std::vector<int> rowptr(m + 1, 0);
+    for (int e = 0; e < nx; ++e)
+        for (long long p = A->colptr[src_col[e]]; p < A->colptr[src_col[e] + 1]; ++p) rowptr[A->rowind[p] + 1]++;
+    for (int i = 0; i < m; ++i) rowptr[i + 1] += rowptr[i];
+    std::vector<int> colidx(rowptr[m]);
+    std::vector<double> val(rowptr[m]);
+    {
+        std::vector<int> fill(rowptr.begin(), rowptr.end() - 1);
+        for (int e = 0; e < nx; ++e)
+            for (long long p = A->colptr[src_col[e]]; p < A->colptr[src_col[e] + 1]; ++p) {
+                const int r = A->rowind[p];
+                colidx[fill[r]] = e;
+                val[fill[r]++] = A->val[p] * wgt[e];
+            }
+    }
+    // A_f in CSC and CSR
+    std::vector<int> fptr(k + 1, 0), frow;
+    std::vector<double> fval;
+    for (int j = 0; j < k; ++j) {
+        const int e = fcols[j];
+        for (long long p = A->colptr[src_col[e]]; p < A->colptr[src_col[e] + 1]; ++p) {
+            frow.push_back(A->rowind[p]);
+            fval.push_back(A->val[p]);
+        }
+        fptr[j + 1] = (int)frow.size();
+    }
+    std::vector<int> frptr(m + 1, 0);
+    for (int r : frow) frptr[r + 1]++;
+    for (int i = 0; i < m; ++i) frptr[i + 1] += frptr[i];
+    std::vector<int> frcol(frow.size());
+    std::vector<double> frval(frow.size());
+    {
+        std::vector<int> fill(frptr.begin(), frptr.end() - 1);
+        for (int j = 0; j < k; ++j)
+            for (int p = fptr[j]; p < fptr[j + 1]; ++p) {
+                frcol[fill[frow[p]]] = j;
+                frval[fill[frow[p]]++] = fval[p];
+            }
+    }
+    std::vector<double> dinv(m);
+    for (int i = 0; i < m; ++i) dinv[i] = 1.0 / d[i];
+    // S = W_f^{-1} + A_f^T D^{-1} A_f and its Cholesky factor.  In full-vec terms
+    // A_f A_f^T sums both copies of an off-diagonal column, i.e. A_f W_f A_f^T with
+    // W_f = diag(wgt), and the matrix inversion lemma then needs W_f^{-1} in place of I.
+    std::vector<double> S((size_t)k * k, 0.0);
+    for (int j = 0; j < k; ++j) S[(size_t)j * k + j] = 1.0 / wgt[fcols[j]];
+    for (int r = 0; r < m; ++r)
+        for (int p = frptr[r]; p < frptr[r + 1]; ++p)
+            for (int q = frptr[r]; q < frptr[r + 1]; ++q)
+                S[(size_t)frcol[p] * k + frcol[q]] += frval[p] * frval[q] * dinv[r];
+    cholesky(S, k);
+    std::vector<double> Lcol, Lrow, Ldinv(k);
+    Lcol.reserve((size_t)k * (k + 1) / 2);
+    Lrow.reserve((size_t)k * (k + 1) / 2);
+    for (int j = 0; j < k; ++j)
+        for (int i = j; i < k; ++i) Lcol.push_back(S[(size_t)i * k + j]);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j <= i; ++j) Lrow.push_back(S[(size_t)i * k + j]);
+    for (int j = 0; j < k; ++j) Ldinv[j] = 1.0 / S[(size_t)j * k + j];
+
+    // h = M^{-1} zeta, zeta = (c, -b): the same Woodbury route, in FP64 on the host
+    std::vector<double> bv(b, b + m);
+    std::vector<double> x(m);
+    for (int r = 0; r < m; ++r) {
+        double acc = -bv[r];
+        for (int p = rowptr[r]; p < rowptr[r + 1]; ++p) acc -= val[p] * cs[colidx[p]];
+        x[r] = acc * dinv[r];
+    }
+    std::vector<double> zq(k, 0.0);
+    for (int j = 0; j < k; ++j)
+        for (int p = fptr[j]; p < fptr[j + 1]; ++p) zq[j] += fval[p] * x[frow[p]];
+    for (int j = 0; j < k; ++j) {   // forward
+        double s = zq[j];
+        for (int p = 0; p < j; ++p) s -= S[(size_t)j * k + p] * zq[p];
+        zq[j] = s / S[(size_t)j * k + j];
+    }
+    for (int j = k - 1; j >= 0; --j) {   // backward
+        double s = zq[j];
+        for (int p = j + 1; p < k; ++p) s -= S[(size_t)p * k + j] * zq[p];
+        zq[j] = s / S[(size_t)j * k + j];
+    }
+    std::vector<double> h(nx + m);
+    for (int r = 0; r < m; ++r) {
+        double acc = 0.0;
+        for (int p = frptr[r]; p < frptr[r + 1]; ++p) acc += frval[p] * zq[frcol[p]];
+        h[nx + r] = x[r] - dinv[r] * acc;
+    }
+    for (int e = 0; e < nx; ++e) {
+        double acc = cs[e];
+        if (colrow[e] >= 0) acc += colval[e] * h[nx + colrow[e]];
+        else if (colrow[e] <= -2) {
+            const int j = -2 - colrow[e];
+            for (int p = fptr[j]; p < fptr[j + 1]; ++p) acc += fval[p] * h[nx + frow[p]];
+        }
+        h[e] = acc;
+    }
+    double ch = 0.0, bh = 0.0, nb = 0.0, nc = 0.0;
+    for (int e = 0; e < nx; ++e) {
+        ch += cw[e] * h[e];
+        nc += cw[e] * cs[e];
+    }
+    for (int r = 0; r < m; ++r) {
+        bh += bv[r] * h[nx + r];
+        nb += bv[r] * bv[r];
+    }
+    const double eta = 1.0 + ch - bh;
+
+    // upload
+    hipStream_t st = w->stream;
+    ProbDesc &P = w->desc;
+    std::memset(&P, 0, sizeof(P));
+    P.m = m;
+    P.nx = nx;
+    P.nfree = K->n_free;
+    P.k = k;
+    P.nblk = K->n_psd;
+    P.nmax = w->nmax;
+    for (int bk = 0; bk < K->n_psd; ++bk) {
+        P.blk_N[bk] = K->N[bk];
+        P.blk_off[bk] = w->off_svec[bk];
+    }
+    DeviceArena &M = w->mem;
+    auto up_i = [&](const std::vector<int> &v) {
+        int *p = M.alloc<int>(v.size());
+        if (!p) throw Status(SOS_E_NOMEM, "hipMalloc failed");
+        upload(p, v, st);
+        return p;
+    };
+    auto up_d = [&](const std::vector<double> &v) {
+        double *p = M.alloc<double>(v.size());
+        if (!p) throw Status(SOS_E_NOMEM, "hipMalloc failed");
+        upload(p, v, st);
+        return p;
+    };
+    auto up_f = [&](const std::vector<double> &v) {
+        float *p = M.alloc<float>(v.size());
+        if (!p) throw Status(SOS_E_NOMEM, "hipMalloc failed");
+        std::vector<float> f = to_f32(v);
+        upload(p, f, st);
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        return p;
+    };
+    P.rowptr = up_i(rowptr);
+    P.colidx = up_i(colidx);
+    P.val64 = up_d(val);
+    P.val32 = up_f(val);
+    P.colrow = up_i(colrow);
+    P.colval64 = up_d(colval);
+    P.colval32 = up_f(colval);
+    P.fptr = up_i(fptr);
+    P.frow = up_i(frow);
+    P.fval64 = up_d(fval);
+    P.fval32 = up_f(fval);
+    P.frptr = up_i(frptr);
+    P.frcol = up_i(frcol);
+    P.frval64 = up_d(frval);
+    P.frval32 = up_f(frval);
+    P.dinv64 = up_d(dinv);
+    P.dinv32 = up_f(dinv);
+    P.Lcol = up_d(Lcol);
+    P.Lrow = up_d(Lrow);
+    P.Ldinv = up_d(Ldinv);
+    P.h64 = up_d(h);
+    P.h32 = up_f(h);
+    P.b64 = up_d(bv);
+    P.b32 = up_f(bv);
+    P.c64 = up_d(cs);
+    P.c32 = up_f(cs);
+    P.cw64 = up_d(cw);
+    P.cw32 = up_f(cw);
+    P.wgt64 = up_d(wgt);
+    P.eta = eta;
+    P.nb = std::sqrt(nb);
+    P.nc = std::sqrt(nc);
+    P.u64 = M.alloc<double>(nx + m);
+    P.v64 = M.alloc<double>(nx);
+    P.u32 = M.alloc<float>(nx + m);
+    P.v32 = M.alloc<float>(nx);
+    P.tk = M.alloc<double>(2);
+    P.out = M.alloc<double>(SOS_OUT_N);
+    if (!P.u64 || !P.v64 || !P.u32 || !P.v32 || !P.tk || !P.out) throw Status(SOS_E_NOMEM, "hipMalloc failed");
+    hip_check(hipMemsetAsync(P.u64, 0, sizeof(double) * (nx + m), st), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(P.v64, 0, sizeof(double) * nx, st), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(P.u32, 0, sizeof(float) * (nx + m), st), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(P.v32, 0, sizeof(float) * nx, st), "hipMemsetAsync");
+    const double tk0[2] = {1.0, 1.0};
+    hip_check(hipMemcpyAsync(P.tk, tk0, sizeof(tk0), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    w->d_desc = M.alloc<ProbDesc>(1);
+    w->d_counter = M.alloc<int>(1);
+    w->d_order = M.alloc<int>(1);
+    if (!w->d_desc || !w->d_counter || !w->d_order) throw Status(SOS_E_NOMEM, "hipMalloc failed");
+    hip_check(hipMemcpyAsync(w->d_desc, &P, sizeof(P), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    const int zero = 0;
+    hip_check(hipMemcpyAsync(w->d_order, &zero, sizeof(int), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    // per-workgroup areas for a single-problem launch
+    w->eig_ld = std::max(w->nmax, 1);
+    w->work_stride = (long long)(((m + 63) & ~63) + nx + 64) * sizeof(double);
+    w->eig_stride = (long long)2 * w->eig_ld * std::max(w->nmax, 1) * sizeof(double) + 256;
+    w->d_work = M.alloc<char>(w->work_stride);
+    w->d_eig = M.alloc<char>(w->eig_stride);
+    if (!w->d_work || !w->d_eig) throw Status(SOS_E_NOMEM, "hipMalloc failed");
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    w->active64 = true;
+    hip_check(hipEventCreate(&w->ev0), "hipEventCreate");
+    hip_check(hipEventCreate(&w->ev1), "hipEventCreate");
+}
+
+RunParams single_params(sos_work *w, int mode, int iters, int min_iters, double tol) {
+    RunParams rp{};
+    rp.probs = w->d_desc;
+    rp.order = w->d_order;
+    rp.counter = w->d_counter;
+    rp.count = 1;
+    rp.mode = mode;
+    rp.iters = iters;
+    rp.min_iters = min_iters;
+    rp.check_every = w->st.check_every;
+    rp.tol = tol;
+    rp.alpha = w->st.alpha;
+    rp.work = w->d_work;
+    rp.work_stride = w->work_stride;
+    rp.eig = w->d_eig;
+    rp.eig_stride = w->eig_stride;
+    rp.eig_ld = w->eig_ld;
+    rp.max_sweeps = 60;
+    return rp;
+}
+
+void run_single(sos_work *w, int fp64, const RunParams &rp) {
+    if (sos_launch_reset(w->d_counter, w->stream)) throw Status(SOS_E_HIP, "reset launch failed");
+    if (sos_launch_admm(fp64, w->threads, 1, rp, w->stream)) throw Status(SOS_E_HIP, "solver launch failed");
+}
+
+void set_active(sos_work *w, bool to64) {
+    if (w->active64 == to64) return;
+    if (sos_launch_cast_state(w->d_desc, nullptr, 1, to64 ? 1 : 0, w->stream, w->nx + w->m))
+        throw Status(SOS_E_HIP, "cast launch failed");
+    w->active64 = to64;
+}
+
+void read_info(sos_work *w, const double *o, sos_info *info, int iters, int polish) {
+    if (!info) return;
+    info->status = (int)o[SOS_OUT_STATUS];
+    info->iters = iters;
+    info->k_lowrank = w->k;
+    info->polish_iters = polish;
+    info->pobj = o[SOS_OUT_POBJ];
+    info->dobj = o[SOS_OUT_DOBJ];
+    info->res_pri = o[SOS_OUT_RP];
+    info->res_dual = o[SOS_OUT_RD];
+    info->gap = o[SOS_OUT_GAP];
+    info->tau = o[SOS_OUT_TAU];
+    info->kappa = o[SOS_OUT_KAPPA];
+    info->setup_ms = w->setup_ms;
+    info->solve_ms = w->last_ms;
+}
+
+template <typename F>
+int guarded(sos_work *w, F &&f) {
+    try {
+        f();
+        return SOS_OK;
+    } catch (const Status &s) {
+        if (w) w->err = s.msg;
+        return s.code;
+    } catch (const std::bad_alloc &) {
+        if (w) w->err = "host allocation failed";
+        return SOS_E_NOMEM;
+    }
+}
+
+// full-vec host vector -> lower triangle (xi part of u or v), averaging (i,j) and (j,i)
+void full_to_svec(const sos_work *w, const double *x, std::vector<double> &out) {
+    out.assign(w->nx, 0.0);
+    for (int e = 0; e < w->nfree; ++e) out[e] = x[e];
+    for (size_t bk = 0; bk < w->N.size(); ++bk) {
+        const int N = w->N[bk];
+        const double *X = x + w->off_full[bk];
+        for (int j = 0; j < N; ++j)
+            for (int i = j; i < N; ++i) {
+                const int e = w->off_svec[bk] + svec_index(i, j, N);
+                out[e] = (i == j) ? X[j * N + i] : 0.5 * (X[j * N + i] + X[i * N + j]);
+            }
+    }
+}
+
+void svec_to_full(const sos_work *w, const std::vector<double> &s, double scale, double *x) {
+    for (int e = 0; e < w->nfree; ++e) x[e] = s[e] * scale;
+    for (size_t bk = 0; bk < w->N.size(); ++bk) {
+        const int N = w->N[bk];
+        double *X = x + w->off_full[bk];
+        for (int j = 0; j < N; ++j)
+            for (int i = j; i < N; ++i) {
+                const double val = s[w->off_svec[bk] + svec_index(i, j, N)] * scale;
+                X[j * N + i] = X[i * N + j] = val;
+            }
+    }
+}
+
+void fetch_state(const sos_work *w, std::vector<double> &u, std::vector<double> &v, double tk[2]) {
+    const int nu = w->nx + w->m, nv = w->nx;
+    u.resize(nu);
+    v.resize(nv);
+    if (w->active64) {
+        hip_check(hipMemcpyAsync(u.data(), w->desc.u64, nu * sizeof(double), hipMemcpyDeviceToHost, w->stream), "copy");
+        hip_check(hipMemcpyAsync(v.data(), w->desc.v64, nv * sizeof(double), hipMemcpyDeviceToHost, w->stream), "copy");
+    } else {
+        std::vector<float> uf(nu), vf(nv);
+        hip_check(hipMemcpyAsync(uf.data(), w->desc.u32, nu * sizeof(float), hipMemcpyDeviceToHost, w->stream), "copy");
+        hip_check(hipMemcpyAsync(vf.data(), w->desc.v32, nv * sizeof(float), hipMemcpyDeviceToHost, w->stream), "copy");
+        hip_check(hipStreamSynchronize(w->stream), "sync");
+        for (int i = 0; i < nu; ++i) u[i] = uf[i];
+        for (int i = 0; i < nv; ++i) v[i] = vf[i];
+    }
+    hip_check(hipMemcpyAsync(tk, w->desc.tk, 2 * sizeof(double), hipMemcpyDeviceToHost, w->stream), "copy");
+    hip_check(hipStreamSynchronize(w->stream), "sync");
+}
+
+void push_state(sos_work *w, const std::vector<double> &u, const std::vector<double> &v, const double tk[2]) {
+    const int nu = w->nx + w->m, nv = w->nx;
+    std::vector<float> uf(u.begin(), u.end()), vf(v.begin(), v.end());
+    hip_check(hipMemcpyAsync(w->desc.u64, u.data(), nu * sizeof(double), hipMemcpyHostToDevice, w->stream), "copy");
+    hip_check(hipMemcpyAsync(w->desc.v64, v.data(), nv * sizeof(double), hipMemcpyHostToDevice, w->stream), "copy");
+    hip_check(hipMemcpyAsync(w->desc.u32, uf.data(), nu * sizeof(float), hipMemcpyHostToDevice, w->stream), "copy");
+    hip_check(hipMemcpyAsync(w->desc.v32, vf.data(), nv * sizeof(float), hipMemcpyHostToDevice, w->stream), "copy");
+    hip_check(hipMemcpyAsync(w->desc.tk, tk, 2 * sizeof(double), hipMemcpyHostToDevice, w->stream), "copy");
+    hip_check(hipStreamSynchronize(w->stream), "sync");
+    w->active64 = true;
+}
+
+double json_num(const char *js, const char *key, double dflt) {
+    if (!js) return dflt;
+    std::string pat = std::string("\"") + key + "\"";
+    const char *p = std::strstr(js, pat.c_str());
+    if (!p) return dflt;
+    p = std::strchr(p + pat.size(), ':');
+    if (!p) return dflt;
+    return std::strtod(p + 1, nullptr);
+}
+
+int device_cu_count() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+    return n;
+}
+
+}   // namespace
+
+extern "C" {
+
+int sos_default_settings(sos_settings *s) {
+    if (!s) return SOS_E_INVAL;
+    default_settings(s);
+    return SOS_OK;
+}
+
+int sos_setup(const sos_csc *A, const double *b, const double *c, const sos_cone *K, const sos_settings *s,
+              void *hip_stream, sos_work **out) {
+    if (!out) return SOS_E_INVAL;
+    *out = nullptr;
+    sos_work *w = nullptr;
+    try {
+        w = new sos_work();
+    } catch (...) {
+        g_setup_error = "host allocation failed";
+        return SOS_E_NOMEM;
+    }
+    if (s) w->st = *s;
+    else default_settings(&w->st);
+    w->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = guarded(w, [&] {
+        check_settings(w->st);
+        w->threads = w->st.block_threads ? w->st.block_threads : 256;
+        build(w, A, b, c, K);
+    });
+    if (rc != SOS_OK) {
+        g_setup_error = w->err;
+        delete w;
+        return rc;
+    }
+    w->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = w;
+    return SOS_OK;
+}
+
+int sos_step(sos_work *w, int32_t iters, sos_info *info) {
+    if (!w || iters < 0) return SOS_E_INVAL;
+    return guarded(w, [&] {
+        const int fp64 = w->st.precision == SOS_FP64;
+        set_active(w, fp64);
+        RunParams rp = single_params(w, RUN_STEP, iters, 0, w->st.tol);
+        hip_check(hipEventRecord(w->ev0, w->stream), "event");
+        run_single(w, fp64, rp);
+        hip_check(hipEventRecord(w->ev1, w->stream), "event");
+        double o[SOS_OUT_N];
+        hip_check(hipMemcpyAsync(o, w->desc.out, sizeof(o), hipMemcpyDeviceToHost, w->stream), "copy");
+        hip_check(hipStreamSynchronize(w->stream), "sync");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, w->ev0, w->ev1), "event");
+        w->last_ms = ms;
+        read_info(w, o, info, iters, 0);
+    });
+}
+
+int sos_solve(sos_work *w, sos_info *info) {
+    if (!w) return SOS_E_INVAL;
+    return guarded(w, [&] {
+        double o[SOS_OUT_N];
+        int total = 0, polish = 0;
+        hip_check(hipEventRecord(w->ev0, w->stream), "event");
+        if (w->st.precision == SOS_FP64) {
+            set_active(w, true);
+            run_single(w, 1, single_params(w, RUN_SOLVE, w->st.max_iters, 0, w->st.tol));
+            hip_check(hipMemcpyAsync(o, w->desc.out, sizeof(o), hipMemcpyDeviceToHost, w->stream), "copy");
+            hip_check(hipStreamSynchronize(w->stream), "sync");
+            total = (int)o[SOS_OUT_ITERS];
+        } else {
+            set_active(w, false);
+            const double tol32 = std::max(w->st.tol, 1e-5);
+            run_single(w, 0, single_params(w, RUN_SOLVE, w->st.max_iters, 0, tol32));
+            hip_check(hipMemcpyAsync(o, w->desc.out, sizeof(o), hipMemcpyDeviceToHost, w->stream), "copy");
+            hip_check(hipStreamSynchronize(w->stream), "sync");
+            const int it32 = (int)o[SOS_OUT_ITERS];
+            set_active(w, true);
+            const int budget = std::max(w->st.polish_iters, w->st.max_iters - it32);
+            run_single(w, 1, single_params(w, RUN_SOLVE, budget, w->st.polish_iters, w->st.tol));
+            hip_check(hipMemcpyAsync(o, w->desc.out, sizeof(o), hipMemcpyDeviceToHost, w->stream), "copy");
+            hip_check(hipStreamSynchronize(w->stream), "sync");
+            polish = (int)o[SOS_OUT_ITERS];
+            total = it32 + polish;
+        }
+        hip_check(hipEventRecord(w->ev1, w->stream), "event");
+        hip_check(hipEventSynchronize(w->ev1), "event");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, w->ev0, w->ev1), "event");
+        w->last_ms = ms;
+        read_info(w, o, info, total, polish);
+    });
+}
+
+int sos_warm_start(sos_work *w, const double *x, const double *y, const double *z, double tau, double kappa) {
+    if (!w || !x || !y || !z) return SOS_E_INVAL;
+    return guarded(w, [&] {
+        if (!(tau >= 0.0) || !(kappa >= 0.0) || (tau == 0.0 && kappa == 0.0) || !std::isfinite(tau) ||
+            !std::isfinite(kappa))
+            throw Status(SOS_E_INVAL, "tau, kappa must be >= 0 and not both zero");
+        for (int e = 0; e < w->nfree; ++e)
+            if (z[e] != 0.0) throw Status(SOS_E_INVAL, "z must vanish on the free variables");
+        for (int i = 0; i < w->n_full; ++i)
+            if (!std::isfinite(x[i]) || !std::isfinite(z[i])) throw Status(SOS_E_INVAL, "non-finite warm start");
+        for (int i = 0; i < w->m; ++i)
+            if (!std::isfinite(y[i])) throw Status(SOS_E_INVAL, "non-finite warm start");
+        std::vector<double> xs, zs;
+        full_to_svec(w, x, xs);
+        full_to_svec(w, z, zs);
+        std::vector<double> u(w->nx + w->m), v(w->nx);
+        for (int e = 0; e < w->nx; ++e) {
+            u[e] = tau * xs[e];
+            v[e] = tau * zs[e];
+        }
+        for (int i = 0; i < w->m; ++i) u[w->nx + i] = tau * y[i];
+        const double tk[2] = {tau, kappa};
+        push_state(w, u, v, tk);
+    });
+}
+
+int sos_get_solution(const sos_work *w, double *x, double *y, double *z) {
+    if (!w) return SOS_E_INVAL;
+    return guarded(const_cast<sos_work *>(w), [&] {
+        std::vector<double> u, v;
+        double tk[2];
+        fetch_state(w, u, v, tk);
+        if (!(tk[0] > 0.0)) throw Status(SOS_E_STATE, "tau == 0: no solution to normalise (certificate state)");
+        const double s = 1.0 / tk[0];
+        if (x) svec_to_full(w, u, s, x);
+        if (z) svec_to_full(w, v, s, z);
+        if (y)
+            for (int i = 0; i < w->m; ++i) y[i] = u[w->nx + i] * s;
+    });
+}
+
+int sos_get_iterate(const sos_work *w, double *uo, double *vo) {
+    if (!w || !uo || !vo) return SOS_E_INVAL;
+    return guarded(const_cast<sos_work *>(w), [&] {
+        std::vector<double> u, v;
+        double tk[2];
+        fetch_state(w, u, v, tk);
+        const int n = w->n_full, m = w->m;
+        svec_to_full(w, u, 1.0, uo);
+        for (int i = 0; i < m; ++i) uo[n + i] = u[w->nx + i];
+        uo[n + m] = tk[0];
+        svec_to_full(w, v, 1.0, vo);
+        for (int i = 0; i < m; ++i) vo[n + i] = 0.0;
+        vo[n + m] = tk[1];
+    });
+}
+
+int sos_set_iterate(sos_work *w, const double *uo, const double *vo) {
+    if (!w || !uo || !vo) return SOS_E_INVAL;
+    return guarded(w, [&] {
+        const int n = w->n_full, m = w->m;
+        for (int i = 0; i < m; ++i)
+            if (vo[n + i] != 0.0) throw Status(SOS_E_INVAL, "the s part of v must be zero");
+        for (int e = 0; e < w->nfree; ++e)
+            if (vo[e] != 0.0) throw Status(SOS_E_INVAL, "z must vanish on the free variables");
+        for (int i = 0; i < n + m + 1; ++i)
+            if (!std::isfinite(uo[i]) || !std::isfinite(vo[i])) throw Status(SOS_E_INVAL, "non-finite state");
+        std::vector<double> us, vs;
+        full_to_svec(w, uo, us);
+        full_to_svec(w, vo, vs);
+        std::vector<double> u(w->nx + m), v(w->nx);
+        for (int e = 0; e < w->nx; ++e) {
+            u[e] = us[e];
+            v[e] = vs[e];
+        }
+        for (int i = 0; i < m; ++i) u[w->nx + i] = uo[n + i];
+        const double tk[2] = {uo[n + m], vo[n + m]};
+        push_state(w, u, v, tk);
+    });
+}
+
+const char *sos_last_error(const sos_work *w) { return w ? w->err.c_str() : g_setup_error.c_str(); }
+
+void sos_free(sos_work *w) {
+    if (!w) return;
+    if (w->stream) (void)hipStreamSynchronize(w->stream);
+    else (void)hipDeviceSynchronize();
+    if (w->ev0) (void)hipEventDestroy(w->ev0);
+    if (w->ev1) (void)hipEventDestroy(w->ev1);
+    w->mem.release();
+    delete w;
+}
+
+int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_json, sos_batch **out) {
+    if (!out || count < 1 || !probs) return SOS_E_INVAL;
+    *out = nullptr;
+    sos_batch *B = new (std::nothrow) sos_batch();
+    if (!B) return SOS_E_NOMEM;
+    int rc = guarded(nullptr, [&] {
+        B->count = count;
+        B->probs.assign(probs, probs + count);
+        for (int i = 0; i < count; ++i)
+            if (!probs[i]) throw Status(SOS_E_INVAL, "null handle in batch");
+        B->st = probs[0]->st;
+        B->fp64 = B->st.precision == SOS_FP64;
+        for (int i = 1; i < count; ++i)
+            if (probs[i]->st.precision != B->st.precision) throw Status(SOS_E_INVAL, "mixed precisions in one batch");
+        B->threads = (int)json_num(schedule_json, "block_threads", B->st.block_threads ? B->st.block_threads : 256);
+        B->wg_per_cu = (int)json_num(schedule_json, "wg_per_cu", 2);
+        B->max_sweeps = (int)json_num(schedule_json, "max_sweeps", 60);
+        B->use_graph = json_num(schedule_json, "use_graph", 1) != 0.0;
+        if (B->threads < 64 || B->threads > 1024 || (B->threads & (B->threads - 1)))
+            throw Status(SOS_E_INVAL, "schedule block_threads must be a power of two in 64..1024");
+        if (B->wg_per_cu < 1 || B->wg_per_cu > 16) throw Status(SOS_E_INVAL, "schedule wg_per_cu must be 1..16");
+        hip_check(hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking), "hipStreamCreate");
+        std::vector<ProbDesc> descs(count);
+        int mmax = 0, nxmax = 0, nmax = 1;
+        std::vector<double> cost(count);
+        for (int i = 0; i < count; ++i) {
+            descs[i] = probs[i]->desc;
+            mmax = std::max(mmax, probs[i]->m);
+            nxmax = std::max(nxmax, probs[i]->nx);
+            nmax = std::max(nmax, probs[i]->nmax);
+            double c3 = 0.0;
+            for (int N : probs[i]->N) c3 += (double)N * N * N;
+            cost[i] = c3 + probs[i]->nx + probs[i]->m;
+            B->max_len = std::max(B->max_len, probs[i]->nx + probs[i]->m);
+        }
+        B->d_out = B->mem.alloc<double>((size_t)count * SOS_OUT_N);
+        if (!B->d_out) throw Status(SOS_E_NOMEM, "hipMalloc failed");
+        for (int i = 0; i < count; ++i) descs[i].out = B->d_out + (size_t)i * SOS_OUT_N;
+        std::vector<int> order(count);
+        for (int i = 0; i < count; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        B->d_desc = B->mem.alloc<ProbDesc>(count);
+        B->d_order = B->mem.alloc<int>(count);
+        B->d_counter = B->mem.alloc<int>(1);
+        if (!B->d_desc || !B->d_order || !B->d_counter) throw Status(SOS_E_NOMEM, "hipMalloc failed");
+        hip_check(hipMemcpy(B->d_desc, descs.data(), sizeof(ProbDesc) * count, hipMemcpyHostToDevice), "copy");
+        hip_check(hipMemcpy(B->d_order, order.data(), sizeof(int) * count, hipMemcpyHostToDevice), "copy");
+        const int cus = device_cu_count();
+        B->grid = std::min(count, cus * B->wg_per_cu);
+        B->eig_ld = nmax;
+        B->work_stride = (long long)(((mmax + 63) & ~63) + nxmax + 64) * sizeof(double);
+        B->eig_stride = (long long)2 * B->eig_ld * nmax * sizeof(double) + 256;
+        B->d_work = B->mem.alloc<char>((size_t)B->work_stride * B->grid);
+        B->d_eig = B->mem.alloc<char>((size_t)B->eig_stride * B->grid);
+        if (!B->d_work || !B->d_eig) throw Status(SOS_E_NOMEM, "hipMalloc failed");
+        hip_check(hipEventCreate(&B->ev0), "event");
+        hip_check(hipEventCreate(&B->ev1), "event");
+        for (auto &e : B->evp) hip_check(hipEventCreate(&e), "event");
+    });
+    if (rc != SOS_OK) {
+        if (B->stream) (void)hipStreamDestroy(B->stream);
+        delete B;
+        return rc;
+    }
+    *out = B;
+    return SOS_OK;
+}
+
+static RunParams batch_params(sos_batch *B, int mode, int iters, int min_iters, double tol) {
+    RunParams rp{};
+    rp.probs = B->d_desc;
+    rp.order = B->d_order;
+    rp.counter = B->d_counter;
+    rp.count = B->count;
+    rp.mode = mode;
+    rp.iters = iters;
+    rp.min_iters = min_iters;
+    rp.check_every = B->st.check_every;
+    rp.tol = tol;
+    rp.alpha = B->st.alpha;
+    rp.work = B->d_work;
+    rp.work_stride = B->work_stride;
+    rp.eig = B->d_eig;
+    rp.eig_stride = B->eig_stride;
+    rp.eig_ld = B->eig_ld;
+    rp.max_sweeps = B->max_sweeps;
+    return rp;
+}
+
+static void enqueue_batch(sos_batch *B) {
+    // events around the main solve kernel and the FP64 polish kernel (graph nodes when captured)
+    if (sos_launch_reset(B->d_counter, B->stream)) throw Status(SOS_E_HIP, "reset launch failed");
+    hip_check(hipEventRecord(B->evp[0], B->stream), "event");
+    if (B->fp64) {
+        RunParams rp = batch_params(B, RUN_SOLVE, B->st.max_iters, 0, B->st.tol);
+        if (sos_launch_admm(1, B->threads, B->grid, rp, B->stream)) throw Status(SOS_E_HIP, "launch failed");
+        hip_check(hipEventRecord(B->evp[1], B->stream), "event");
+    } else {
+        RunParams rp = batch_params(B, RUN_SOLVE, B->st.max_iters, 0, std::max(B->st.tol, 1e-5));
+        if (sos_launch_admm(0, B->threads, B->grid, rp, B->stream)) throw Status(SOS_E_HIP, "launch failed");
+        hip_check(hipEventRecord(B->evp[1], B->stream), "event");
+        if (sos_launch_cast_state(B->d_desc, nullptr, B->count, 1, B->stream, B->max_len))
+            throw Status(SOS_E_HIP, "cast launch failed");
+        if (sos_launch_reset(B->d_counter, B->stream)) throw Status(SOS_E_HIP, "reset launch failed");
+        hip_check(hipEventRecord(B->evp[2], B->stream), "event");
+        RunParams rp2 = batch_params(B, RUN_SOLVE, std::max(B->st.polish_iters, B->st.max_iters),
+                                     B->st.polish_iters, B->st.tol);
+        rp2.accumulate = 1;
+        if (sos_launch_admm(1, B->threads, B->grid, rp2, B->stream)) throw Status(SOS_E_HIP, "launch failed");
+        hip_check(hipEventRecord(B->evp[3], B->stream), "event");
+    }
+}
+
+int sos_batch_solve(sos_batch *B, sos_info *infos) {
+    if (!B || !infos) return SOS_E_INVAL;
+    int rc = guarded(nullptr, [&] {
+        // the handles' current iterate must sit in the copy the solve starts from
+        for (sos_work *w : B->probs) {
+            set_active(w, B->fp64 != 0);
+            hip_check(hipStreamSynchronize(w->stream), "sync");
+        }
+        if (B->use_graph && !B->exec) {
+            hip_check(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal), "capture");
+            try {
+                enqueue_batch(B);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(B->stream, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            hip_check(hipStreamEndCapture(B->stream, &B->graph), "end capture");
+            hip_check(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0), "instantiate");
+        }
+        hip_check(hipEventRecord(B->ev0, B->stream), "event");
+        if (B->use_graph) hip_check(hipGraphLaunch(B->exec, B->stream), "graph launch");
+        else enqueue_batch(B);
+        hip_check(hipEventRecord(B->ev1, B->stream), "event");
+        std::vector<double> o((size_t)B->count * SOS_OUT_N);
+        hip_check(hipMemcpyAsync(o.data(), B->d_out, o.size() * sizeof(double), hipMemcpyDeviceToHost, B->stream),
+                  "copy");
+        hip_check(hipStreamSynchronize(B->stream), "sync");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, B->ev0, B->ev1), "event");
+        B->last_ms = ms;
+        float p0 = 0.f, p1 = 0.f;
+        if (hipEventElapsedTime(&p0, B->evp[0], B->evp[1]) != hipSuccess) p0 = -1.f;
+        if (!B->fp64 && hipEventElapsedTime(&p1, B->evp[2], B->evp[3]) != hipSuccess) p1 = -1.f;
+        B->phase_ms[0] = p0;
+        B->phase_ms[1] = B->fp64 ? 0.0 : p1;
+        for (int i = 0; i < B->count; ++i) {
+            sos_work *w = B->probs[i];
+            w->active64 = true;
+            w->last_ms = ms;
+            const double *oi = o.data() + (size_t)i * SOS_OUT_N;
+            read_info(w, oi, &infos[i], (int)oi[SOS_OUT_TOTAL], B->fp64 ? 0 : (int)oi[SOS_OUT_ITERS]);
+        }
+    });
+    return rc;
+}
+
+int sos_batch_reset(sos_batch *B) {
+    if (!B) return SOS_E_INVAL;
+    return guarded(nullptr, [&] {
+        for (sos_work *w : B->probs) hip_check(hipStreamSynchronize(w->stream), "sync");
+        if (sos_launch_reset_state(B->d_desc, B->count, B->max_len, B->stream))
+            throw Status(SOS_E_HIP, "reset launch failed");
+        hip_check(hipStreamSynchronize(B->stream), "sync");
+        for (sos_work *w : B->probs) w->active64 = true;
+    });
+}
+
+double sos_batch_phase_ms(const sos_batch *B, int32_t phase) {
+    if (!B || phase < 0 || phase > 1) return -1.0;
+    return B->phase_ms[phase];
+}
+
+double sos_batch_last_ms(const sos_batch *B) { return B ? B->last_ms : 0.0; }
+
+void sos_batch_free(sos_batch *B) {
+    if (!B) return;
+    if (B->stream) (void)hipStreamSynchronize(B->stream);
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    if (B->ev0) (void)hipEventDestroy(B->ev0);
+    if (B->ev1) (void)hipEventDestroy(B->ev1);
+    for (auto &e : B->evp)
+        if (e) (void)hipEventDestroy(e);
+    B->mem.release();
+    if (B->stream) (void)hipStreamDestroy(B->stream);
+    delete B;
+}
+
+}   // extern "C"

@@ -1,0 +1,89 @@
+// Internal layout shared by the host library and the gfx950 kernels.
+//
+// One problem on the device (all arrays device-resident):
+//   xi = [ free variables (n_free) | block 0 lower | block 1 lower | ... ]   length nx
+// where "lower" is the lower triangle of the block, by columns, UNSCALED: entry
+// (i,j), i >= j, holds X_ij.  The full column-stacked vec of the paper counts every
+// off-diagonal entry twice, so inner products and norms over xi carry the weight
+// wgt = 2 off the diagonal (1 on it and on free variables), and the row gather
+// A xi uses A's value times that weight.  Iterates therefore equal the lower
+// triangles of the paper's full-vec iterates, and conversion at the ABI is a copy.
+//   u  = [ xi | y (m) ]  (tau kept in FP64 in tk[0])
+//   v  = [ z  ]          (s is identically zero for every iterate, kappa in tk[1])
+// A = [A_f A_s]: A_s columns have at most one nonzero, so A_s A_s^T is diagonal
+// (Proposition 1); A_f holds the free columns and every column with two or more
+// nonzeros (weighted blocks, Section VI).
+#pragma once
+#include <stdint.h>
+
+#define SOS_MAX_BLOCKS 8
+#define SOS_KMAX_LDS 1024   // largest A_f width whose k-vector is kept in LDS
+
+struct ProbDesc {
+    int m, nx, nfree, k, nblk, nmax;
+    int blk_N[SOS_MAX_BLOCKS];
+    int blk_off[SOS_MAX_BLOCKS];      // svec offset of each PSD block inside xi
+
+    // all of A in CSR over the lower-triangle columns, values already times wgt
+    const int *rowptr, *colidx;
+    const double *val64; const float *val32;
+    // per column: row of its single nonzero (A_s), -1 if empty, -2-j for A_f column j (unscaled values)
+    const int *colrow;
+    const double *colval64; const float *colval32;
+    // A_f in CSC (k columns) and CSR (rows -> A_f column index)
+    const int *fptr, *frow;
+    const double *fval64; const float *fval32;
+    const int *frptr, *frcol;
+    const double *frval64; const float *frval32;
+    // 1/d, d = 1 + diag(A_s A_s^T)
+    const double *dinv64; const float *dinv32;
+    // Cholesky factor of S = W_f^{-1} + A_f^T D^{-1} A_f (W_f = wgt on the A_f columns),
+    // packed lower, by columns and by rows
+    const double *Lcol, *Lrow, *Ldinv;
+    // h = M^{-1} zeta (nx + m), b (m), c (nx), cw = wgt * c (nx), wgt (nx)
+    const double *h64; const float *h32;
+    const double *b64; const float *b32;
+    const double *c64; const float *c32;
+    const double *cw64; const float *cw32;
+    const double *wgt64;
+    double eta, nb, nc;
+
+    // iterate
+    double *u64, *v64;
+    float  *u32, *v32;
+    double *tk;          // [0] tau, [1] kappa
+    double *out;         // SOS_OUT_* below
+};
+
+enum {
+    SOS_OUT_STATUS = 0, SOS_OUT_ITERS, SOS_OUT_POBJ, SOS_OUT_DOBJ, SOS_OUT_RP, SOS_OUT_RD, SOS_OUT_GAP,
+    SOS_OUT_TAU, SOS_OUT_KAPPA, SOS_OUT_CX, SOS_OUT_BY, SOS_OUT_TOTAL, SOS_OUT_N
+};
+
+enum { RUN_STEP = 0, RUN_SOLVE = 1 };
+
+struct RunParams {
+    ProbDesc *probs;        // device array
+    const int *order;       // queue order (indices into probs)
+    int *counter;           // device queue head
+    int count;
+    int mode;               // RUN_STEP | RUN_SOLVE
+    int iters;              // RUN_STEP: exact count; RUN_SOLVE: max iterations
+    int min_iters;          // RUN_SOLVE: no stopping test before this many iterations
+    int check_every;
+    double tol, alpha;
+    void *work;             // per-workgroup affine work area
+    long long work_stride;  // bytes
+    void *eig;              // per-workgroup eigensolver area (global)
+    long long eig_stride;   // bytes
+    int eig_ld;             // leading dimension of the eigensolver matrices
+    int max_sweeps;
+    int accumulate;         // 0: out[TOTAL] = iterations of this launch; 1: out[TOTAL] += them
+};
+
+// host-side launchers implemented in sos_kernels.hip
+int sos_launch_admm(int fp64, int threads, int grid, const RunParams &rp, void *stream);
+int sos_launch_reset(int *counter, void *stream);
+int sos_launch_cast_state(const ProbDesc *probs_dev, const int *ids, int count, int to64, void *stream,
+                          int max_len);
+int sos_launch_reset_state(const ProbDesc *probs_dev, int count, int max_len, void *stream);

@@ -1,0 +1,210 @@
+"""GPU parity: the gfx950 library against the FP64 CPU oracle, through the C ABI.
+
+Bar (FP64 form): iterates after k identical steps agree to 1e-9 relative (both are
+exact up to rounding, and one ADMM step is nonexpansive, so rounding does not grow);
+solved objective values agree to 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle.admm import Oracle
+from sosgen import families as F
+
+pytestmark = pytest.mark.gpu
+
+ITER_RTOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1708_04174_amd import binding
+    binding.load()
+    return binding
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(1.0, np.linalg.norm(b))
+
+
+def _step_parity(B, prob, ks, settings=None, tag=""):
+    o = Oracle.from_problem(prob)
+    w = B.setup_problem(prob, settings)
+    u, v = o.initial()
+    done = 0
+    for k in ks:
+        B.sos_step(w, k - done)
+        u, v = o.run(k - done, u, v)
+        done = k
+        ug, vg = B.sos_get_iterate(w)
+        eu, ev = _rel(ug, u), _rel(vg, v)
+        print(f"[parity] {tag} k={k} |du|={eu:.2e} |dv|={ev:.2e}", flush=True)
+        assert eu <= ITER_RTOL and ev <= ITER_RTOL, (tag, k, eu, ev)
+    w.free()
+
+
+SMALL = {
+    "c1_seed0": lambda: F.FAMILIES["c1"](0),
+    "univariate": lambda: F.univariate([1.0, 0.0, -2.0, 0.0, 1.0]),
+    "ball_n3_weighted": lambda: F.pop_ball(3, 2),
+    "example_pop_n4": lambda: F.example_pop(4),
+    "lyapunov_n2": lambda: F.lyapunov_from_field(2, F.lyapunov_field(2, np.random.default_rng(4))[2]),
+    "lyapunov_c5_seed0": lambda: F.FAMILIES["c5"](0),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_step_parity_small(B, name):
+    _step_parity(B, SMALL[name](), [1, 2, 7, 30], tag=name)
+
+
+def test_step_parity_columns_partition(B):
+    # A_f = only the columns with two or more nonzeros: k = 0 for a POP, same iterates
+    s = B.sos_default_settings(partition=B.SOS_PART_COLUMNS)
+    _step_parity(B, F.FAMILIES["c1"](1), [1, 5, 25], settings=s, tag="c1_columns")
+
+
+@pytest.mark.parametrize("threads", [64, 128, 512])
+def test_step_parity_launch_shapes(B, threads):
+    s = B.sos_default_settings(block_threads=threads)
+    _step_parity(B, F.pop_ball(3, 4), [3, 12], settings=s, tag=f"ball3_t{threads}")
+
+
+def test_step_parity_c3_full_size(B):
+    # constrained quartic POP on the unit ball, n = 16: Gram blocks 153 and 17, m = 4845, k = 154
+    _step_parity(B, F.FAMILIES["c3"](0), [1, 3], tag="c3_full")
+
+
+def test_step_parity_c2_full_size(B):
+    # unconstrained quartic POP, n = 20: Gram block 231, m = 10626
+    _step_parity(B, F.FAMILIES["c2"](0), [1, 2], tag="c2_full")
+
+
+CLOSED = [
+    ("x_squared", lambda: F.univariate([0.0, 0.0, 1.0]), 0.0),
+    ("double_well", lambda: F.univariate([1.0, 0.0, -2.0, 0.0, 1.0]), 0.0),
+]
+
+
+@pytest.mark.parametrize("name,make,gamma", CLOSED)
+def test_solve_closed_forms(B, name, make, gamma):
+    s = B.sos_default_settings(tol=1e-9, max_iters=20000)
+    w = B.setup_problem(make(), s)
+    info = B.sos_solve(w)
+    x, y, z = B.sos_get_solution(w)
+    print(f"[solve] {name} status={info['status_name']} iters={info['iters']} gamma={x[0]:.3e}", flush=True)
+    assert info["status"] == B.SOS_SOLVED and abs(x[0] - gamma) < 1e-6
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_solve_parity_c1(B, seed):
+    prob = F.FAMILIES["c1"](seed)
+    r = Oracle.from_problem(prob).solve(tol=1e-6, max_iters=20000, check_every=10)
+    s = B.sos_default_settings(tol=1e-6, max_iters=20000, check_every=10)
+    w = B.setup_problem(prob, s)
+    info = B.sos_solve(w)
+    x, y, z = B.sos_get_solution(w)
+    print(f"[solve] c1 seed={seed} gpu iters={info['iters']} gamma={x[0]:.9f} oracle iters={r.iters} "
+          f"gamma={r.x[0]:.9f}", flush=True)
+    assert info["status"] == B.SOS_SOLVED and r.status == 1
+    assert info["iters"] == r.iters
+    assert abs(x[0] - r.x[0]) <= 1e-6 * max(1.0, abs(r.x[0]))
+    assert max(info["res_pri"], info["res_dual"], info["gap"]) <= 1e-6
+
+
+def test_solve_status_certificates(B):
+    for make, status in ((F.infeasible_pop, B.SOS_PRIMAL_INFEASIBLE), (F.unbounded_pop, B.SOS_DUAL_INFEASIBLE)):
+        prob = make()
+        r = Oracle.from_problem(prob).solve(tol=1e-6, max_iters=5000)
+        w = B.setup_problem(prob, B.sos_default_settings(tol=1e-6, max_iters=5000))
+        info = B.sos_solve(w)
+        print(f"[solve] {prob.meta['family']} gpu={info['status_name']} oracle={r.status_name}", flush=True)
+        assert info["status"] == status == r.status and info["iters"] == r.iters
+
+
+def test_checkpoint_resume_is_bitwise(B):
+    prob = F.pop_ball(3, 7)
+    w1 = B.setup_problem(prob)
+    B.sos_step(w1, 17)
+    u_mid, v_mid = B.sos_get_iterate(w1)
+    B.sos_step(w1, 23)
+    u_ref, v_ref = B.sos_get_iterate(w1)
+    w2 = B.setup_problem(prob)
+    B.sos_set_iterate(w2, u_mid, v_mid)
+    B.sos_step(w2, 23)
+    u2, v2 = B.sos_get_iterate(w2)
+    assert np.array_equal(u2, u_ref) and np.array_equal(v2, v_ref)
+
+
+def test_repeat_runs_are_bitwise_equal(B):
+    prob = F.FAMILIES["c5"](3)
+    outs = []
+    for _ in range(2):
+        w = B.setup_problem(prob)
+        B.sos_step(w, 25)
+        outs.append(B.sos_get_iterate(w))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_setup_errors(B):
+    prob = F.FAMILIES["c1"](0)
+    A = prob.A.tolil(copy=True)
+    N = prob.psd_dims[0]
+    A[0, 1 + 1 * N + 0] = A[0, 1 + 1 * N + 0] + 1.0      # break the (i,j)/(j,i) symmetry
+    with pytest.raises(B.SosError) as e:
+        B.sos_setup(A.tocsc(), prob.b, prob.c, prob.n_free, prob.psd_dims)
+    assert e.value.code == B.SOS_E_ASYM
+    with pytest.raises(B.SosError) as e:
+        B.sos_setup(prob.A, prob.b, prob.c, prob.n_free, [N + 1])
+    assert e.value.code == B.SOS_E_INVAL
+    bad = prob.b.copy()
+    bad[3] = np.nan
+    with pytest.raises(B.SosError) as e:
+        B.sos_setup(prob.A, bad, prob.c, prob.n_free, prob.psd_dims)
+    assert e.value.code == B.SOS_E_INVAL
+
+
+def test_batch_fp64_equals_single_solves(B):
+    # one persistent launch over uneven problems gives the same iterates as one launch per problem
+    probs = [F.pop_batch_member(s) for s in range(6)] + [F.pop_ball(3, 1), F.FAMILIES["c5"](1)]
+    s = B.sos_default_settings(tol=1e-5, max_iters=3000)
+    singles = []
+    for p in probs:
+        w = B.setup_problem(p, s)
+        inf = B.sos_solve(w)
+        singles.append((inf, B.sos_get_iterate(w)))
+        w.free()
+    works = [B.setup_problem(p, s) for p in probs]
+    bt = B.sos_batch_setup(works, '{"wg_per_cu": 1}')
+    infos = B.sos_batch_solve(bt)
+    for (inf1, (u1, v1)), inf2, w in zip(singles, infos, works):
+        u2, v2 = B.sos_get_iterate(w)
+        print(f"[batch] {inf1['status_name']} iters {inf1['iters']} vs {inf2['iters']}", flush=True)
+        assert inf1["status"] == inf2["status"] and inf1["iters"] == inf2["iters"]
+        assert np.array_equal(u1, u2) and np.array_equal(v1, v2)
+    # a second solve of the same batch from the cold start repeats the first exactly
+    B.sos_batch_reset(bt)
+    infos2 = B.sos_batch_solve(bt)
+    assert [i["iters"] for i in infos2] == [i["iters"] for i in infos]
+    bt.free()
+
+
+def test_batch_mixed_precision_gamma_error(B):
+    # FP32 bulk + FP64 polish: gamma error against the FP64 oracle, stated per problem
+    probs = [F.pop_batch_member(s) for s in range(8)]
+    s = B.sos_default_settings(tol=1e-4, max_iters=4000, precision=B.SOS_FP32_MIXED, polish_iters=1)
+    works = [B.setup_problem(p, s) for p in probs]
+    bt = B.sos_batch_setup(works)
+    infos = B.sos_batch_solve(bt)
+    for p, inf, w in zip(probs, infos, works):
+        r = Oracle.from_problem(p).solve(tol=1e-7, max_iters=50000)
+        x, _, _ = B.sos_get_solution(w)
+        err = abs(x[0] - r.x[0]) / max(1.0, abs(r.x[0]))
+        print(f"[mixed] seed {p.meta['seed']} N={p.psd_dims[0]} status={inf['status_name']} iters={inf['iters']} "
+              f"(fp64 {inf['polish_iters']}) gamma err {err:.2e} res {max(inf['res_pri'], inf['res_dual'], inf['gap']):.1e}",
+              flush=True)
+        assert inf["status"] == B.SOS_SOLVED
+        assert max(inf["res_pri"], inf["res_dual"], inf["gap"]) <= 1e-4
+        assert err <= 5e-4
+    bt.free()
