@@ -103,6 +103,7 @@ typedef struct {
                                          |c^T xi - b^T y|/tau/(1 + |c^T xi|/tau + |b^T y|/tau), FP64 */
     double  tau, kappa;
     double  setup_ms, solve_ms;
+    double  eig_sweeps;      /* mean eigensolver sweeps per block projection in the last launch */
 } sos_info;
 
 /* Fills *s with tol 1e-4, max_iters 2000, check_every 10, alpha 1, SOS_FP64,

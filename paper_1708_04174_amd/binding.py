@@ -54,7 +54,7 @@ class sos_info(C.Structure):
                 ("polish_iters", C.c_int32), ("pobj", C.c_double), ("dobj", C.c_double),
                 ("res_pri", C.c_double), ("res_dual", C.c_double), ("gap", C.c_double),
                 ("tau", C.c_double), ("kappa", C.c_double), ("setup_ms", C.c_double),
-                ("solve_ms", C.c_double)]
+                ("solve_ms", C.c_double), ("eig_sweeps", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -20,6 +20,9 @@ namespace {
 
 thread_local std::string g_setup_error;
 
+// dynamic LDS a solver launch may take (gfx950: 160 KiB per workgroup, minus the static part)
+const int kLdsBudget = 150 * 1024;
+
 struct DeviceArena {
     std::vector<void *> ptrs;
     ~DeviceArena() { release(); }
@@ -103,6 +106,7 @@ struct sos_batch {
     hipEvent_t evp[4] = {nullptr, nullptr, nullptr, nullptr};   // around the solve and polish kernels
     double last_ms = 0.0, phase_ms[2] = {0.0, 0.0};
     bool use_graph = true;
+    int warm_eig = 1, lds_budget = 0;
     sos_settings st{};
 };
 
@@ -424,14 +428,19 @@ void build(sos_work *w, const sos_csc *A, const double *b, const double *c, cons
     P.v64 = M.alloc<double>(nx);
     P.u32 = M.alloc<float>(nx + m);
     P.v32 = M.alloc<float>(nx);
-    P.tk = M.alloc<double>(2);
+    P.tk = M.alloc<double>(4);
+    long long nvs = 0;
+    for (int bk = 0; bk < K->n_psd; ++bk) nvs += (long long)K->N[bk] * K->N[bk];
+    P.vs64 = M.alloc<double>(nvs);
+    P.vs32 = M.alloc<float>(nvs);
+    if (!P.vs64 || !P.vs32) throw Status(SOS_E_NOMEM, "hipMalloc failed");
     P.out = M.alloc<double>(SOS_OUT_N);
     if (!P.u64 || !P.v64 || !P.u32 || !P.v32 || !P.tk || !P.out) throw Status(SOS_E_NOMEM, "hipMalloc failed");
     hip_check(hipMemsetAsync(P.u64, 0, sizeof(double) * (nx + m), st), "hipMemsetAsync");
     hip_check(hipMemsetAsync(P.v64, 0, sizeof(double) * nx, st), "hipMemsetAsync");
     hip_check(hipMemsetAsync(P.u32, 0, sizeof(float) * (nx + m), st), "hipMemsetAsync");
     hip_check(hipMemsetAsync(P.v32, 0, sizeof(float) * nx, st), "hipMemsetAsync");
-    const double tk0[2] = {1.0, 1.0};
+    const double tk0[4] = {1.0, 1.0, 0.0, 0.0};
     hip_check(hipMemcpyAsync(P.tk, tk0, sizeof(tk0), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
     w->d_desc = M.alloc<ProbDesc>(1);
     w->d_counter = M.alloc<int>(1);
@@ -443,7 +452,7 @@ void build(sos_work *w, const sos_csc *A, const double *b, const double *c, cons
     // per-workgroup areas for a single-problem launch
     w->eig_ld = std::max(w->nmax, 1);
     w->work_stride = (long long)(((m + 63) & ~63) + nx + 64) * sizeof(double);
-    w->eig_stride = (long long)2 * w->eig_ld * std::max(w->nmax, 1) * sizeof(double) + 256;
+    w->eig_stride = (long long)3 * w->eig_ld * std::max(w->nmax, 1) * sizeof(double) + 256;
     w->d_work = M.alloc<char>(w->work_stride);
     w->d_eig = M.alloc<char>(w->eig_stride);
     if (!w->d_work || !w->d_eig) throw Status(SOS_E_NOMEM, "hipMalloc failed");
@@ -471,6 +480,8 @@ RunParams single_params(sos_work *w, int mode, int iters, int min_iters, double 
     rp.eig_stride = w->eig_stride;
     rp.eig_ld = w->eig_ld;
     rp.max_sweeps = 60;
+    rp.warm_eig = 1;
+    rp.lds_budget = kLdsBudget;
     return rp;
 }
 
@@ -501,6 +512,7 @@ void read_info(sos_work *w, const double *o, sos_info *info, int iters, int poli
     info->kappa = o[SOS_OUT_KAPPA];
     info->setup_ms = w->setup_ms;
     info->solve_ms = w->last_ms;
+    info->eig_sweeps = o[SOS_OUT_SWEEPS];
 }
 
 template <typename F>
@@ -571,7 +583,8 @@ void push_state(sos_work *w, const std::vector<double> &u, const std::vector<dou
     hip_check(hipMemcpyAsync(w->desc.v64, v.data(), nv * sizeof(double), hipMemcpyHostToDevice, w->stream), "copy");
     hip_check(hipMemcpyAsync(w->desc.u32, uf.data(), nu * sizeof(float), hipMemcpyHostToDevice, w->stream), "copy");
     hip_check(hipMemcpyAsync(w->desc.v32, vf.data(), nv * sizeof(float), hipMemcpyHostToDevice, w->stream), "copy");
-    hip_check(hipMemcpyAsync(w->desc.tk, tk, 2 * sizeof(double), hipMemcpyHostToDevice, w->stream), "copy");
+    const double tk4[4] = {tk[0], tk[1], 0.0, 0.0};   // new iterate: cached eigenvectors are stale
+    hip_check(hipMemcpyAsync(w->desc.tk, tk4, sizeof(tk4), hipMemcpyHostToDevice, w->stream), "copy");
     hip_check(hipStreamSynchronize(w->stream), "sync");
     w->active64 = true;
 }
@@ -799,6 +812,9 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         B->wg_per_cu = (int)json_num(schedule_json, "wg_per_cu", 2);
         B->max_sweeps = (int)json_num(schedule_json, "max_sweeps", 60);
         B->use_graph = json_num(schedule_json, "use_graph", 1) != 0.0;
+        B->warm_eig = (int)json_num(schedule_json, "warm_eig", 1);
+        B->lds_budget = (int)(json_num(schedule_json, "lds_kb", kLdsBudget / 1024.0) * 1024.0);
+        if (B->lds_budget < 0 || B->lds_budget > kLdsBudget) throw Status(SOS_E_INVAL, "schedule lds_kb out of range");
         if (B->threads < 64 || B->threads > 1024 || (B->threads & (B->threads - 1)))
             throw Status(SOS_E_INVAL, "schedule block_threads must be a power of two in 64..1024");
         if (B->wg_per_cu < 1 || B->wg_per_cu > 16) throw Status(SOS_E_INVAL, "schedule wg_per_cu must be 1..16");
@@ -832,7 +848,7 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         B->grid = std::min(count, cus * B->wg_per_cu);
         B->eig_ld = nmax;
         B->work_stride = (long long)(((mmax + 63) & ~63) + nxmax + 64) * sizeof(double);
-        B->eig_stride = (long long)2 * B->eig_ld * nmax * sizeof(double) + 256;
+        B->eig_stride = (long long)3 * B->eig_ld * nmax * sizeof(double) + 256;
         B->d_work = B->mem.alloc<char>((size_t)B->work_stride * B->grid);
         B->d_eig = B->mem.alloc<char>((size_t)B->eig_stride * B->grid);
         if (!B->d_work || !B->d_eig) throw Status(SOS_E_NOMEM, "hipMalloc failed");
@@ -867,6 +883,8 @@ static RunParams batch_params(sos_batch *B, int mode, int iters, int min_iters, 
     rp.eig_stride = B->eig_stride;
     rp.eig_ld = B->eig_ld;
     rp.max_sweeps = B->max_sweeps;
+    rp.warm_eig = B->warm_eig;
+    rp.lds_budget = B->lds_budget;
     return rp;
 }
 

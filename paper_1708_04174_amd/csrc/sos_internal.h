@@ -51,13 +51,15 @@ struct ProbDesc {
     // iterate
     double *u64, *v64;
     float  *u32, *v32;
-    double *tk;          // [0] tau, [1] kappa
+    double *tk;          // [0] tau, [1] kappa, [2] 1 if vs holds eigenvectors of the last iteration
+    double *vs64;        // per PSD block, its N x N eigenvectors from the last iteration (Jacobi warm start)
+    float *vs32;
     double *out;         // SOS_OUT_* below
 };
 
 enum {
     SOS_OUT_STATUS = 0, SOS_OUT_ITERS, SOS_OUT_POBJ, SOS_OUT_DOBJ, SOS_OUT_RP, SOS_OUT_RD, SOS_OUT_GAP,
-    SOS_OUT_TAU, SOS_OUT_KAPPA, SOS_OUT_CX, SOS_OUT_BY, SOS_OUT_TOTAL, SOS_OUT_N
+    SOS_OUT_TAU, SOS_OUT_KAPPA, SOS_OUT_CX, SOS_OUT_BY, SOS_OUT_TOTAL, SOS_OUT_SWEEPS, SOS_OUT_N
 };
 
 enum { RUN_STEP = 0, RUN_SOLVE = 1 };
@@ -78,6 +80,9 @@ struct RunParams {
     long long eig_stride;   // bytes
     int eig_ld;             // leading dimension of the eigensolver matrices
     int max_sweeps;
+    int warm_eig;           // start each block's Jacobi sweeps from the previous iteration's eigenvectors
+    int lds_budget;         // dynamic LDS bytes the launch may use
+    int lds_mat_off, lds_nmax, lds_nmax_g;   // filled in by the launcher
     int accumulate;         // 0: out[TOTAL] = iterations of this launch; 1: out[TOTAL] += them
 };
 

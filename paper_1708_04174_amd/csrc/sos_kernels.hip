@@ -38,6 +38,7 @@ template <> struct TS<double> {
     __device__ static const double *b(const ProbDesc &P) { return P.b64; }
     __device__ static const double *c(const ProbDesc &P) { return P.c64; }
     __device__ static const double *cw(const ProbDesc &P) { return P.cw64; }
+    __device__ static double *vstore(const ProbDesc &P) { return P.vs64; }
     static constexpr double eps = 2.220446049250313e-16;
 };
 template <> struct TS<float> {
@@ -52,6 +53,7 @@ template <> struct TS<float> {
     __device__ static const float *b(const ProbDesc &P) { return P.b32; }
     __device__ static const float *c(const ProbDesc &P) { return P.c32; }
     __device__ static const float *cw(const ProbDesc &P) { return P.cw32; }
+    __device__ static float *vstore(const ProbDesc &P) { return P.vs32; }
     static constexpr float eps = 1.1920929e-07f;
 };
 
@@ -264,6 +266,8 @@ __device__ __forceinline__ int svec_idx(int i, int j, int N) {   // i >= j
     return j * N - (j * (j - 1)) / 2 + (i - j);
 }
 
+// Round-robin (circle) pairing: in round r of M - 1 rounds, pair kk is (p, q), p < q;
+// every index of 0..M-1 appears once per round and every unordered pair once per sweep.
 __device__ __forceinline__ void rr_pair(int r, int kk, int M, int &p, int &q) {
     if (kk == 0) {
         p = M - 1;
@@ -279,134 +283,255 @@ __device__ __forceinline__ void rr_pair(int r, int kk, int M, int &p, int &q) {
     }
 }
 
+struct EigScratch {
+    int *s_flag;
+    int *s_sweeps;    // Jacobi sweeps run (diagnostic)
+    double *s_red;
+};
+
+// Wave sum with lane 0's result broadcast, so every lane holds the bitwise-same value
+// (a butterfly would leave lane-dependent rounding, and branches on it must not diverge).
+__device__ __forceinline__ double wave_allsum(double x) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    return __shfl(x, 0, 64);
+}
+__device__ __forceinline__ float wave_allsum(float x) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    return __shfl(x, 0, 64);
+}
+
+// Sum over a group of GS consecutive lanes; every lane of the group gets the group's first
+// lane's result, so branches on it are uniform inside the group.
+template <int GS, typename T>
+__device__ __forceinline__ T group_allsum(T x) {
+    for (int off = GS / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, GS);
+    return __shfl(x, 0, GS);
+}
+
+// One-sided Jacobi rotation of the column pair (p, q) of G (and of V) by a group of GS
+// lanes; makes g_p and g_q orthogonal.  Returns true if a rotation was applied.
+template <typename T, int GS>
+__device__ __forceinline__ bool os_rotate_pair(T *__restrict__ G, int ldg, T *__restrict__ V, int ldv, int N, int p,
+                                               int q, T tol, T atol) {
+    constexpr int RPL = 256 / GS;   // rows per lane held in registers (N <= 256)
+    const int gl = threadIdx.x & (GS - 1);
+    T *gp = G + (long long)p * ldg, *gq = G + (long long)q * ldg;
+    T *vp = V + (long long)p * ldv, *vq = V + (long long)q * ldv;
+    T al = 0, be = 0, ga = 0;
+    if (N <= 256) {
+        T xp[RPL], xq[RPL];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+            const int i = gl + GS * t;
+            xp[t] = i < N ? gp[i] : (T)0;
+            xq[t] = i < N ? gq[i] : (T)0;
+        }
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+            al += xp[t] * xp[t];
+            be += xq[t] * xq[t];
+            ga += xp[t] * xq[t];
+        }
+        al = group_allsum<GS>(al);
+        be = group_allsum<GS>(be);
+        ga = group_allsum<GS>(ga);
+        if (!(fabs(ga) > tol * sqrt(al * be)) || !(fabs(ga) > atol * sqrt(al > be ? al : be))) return false;
+        const T ze = (be - al) / ((T)2 * ga);
+        const T tt = (ze >= (T)0 ? (T)1 : (T)-1) / (fabs(ze) + sqrt((T)1 + ze * ze));
+        const T cc = (T)1 / sqrt((T)1 + tt * tt), ss = cc * tt;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+            const int i = gl + GS * t;
+            if (i < N) {
+                gp[i] = cc * xp[t] - ss * xq[t];
+                gq[i] = ss * xp[t] + cc * xq[t];
+                const T a = vp[i], b = vq[i];
+                vp[i] = cc * a - ss * b;
+                vq[i] = ss * a + cc * b;
+            }
+        }
+        return true;
+    }
+    for (int i = gl; i < N; i += GS) {
+        const T a = gp[i], b = gq[i];
+        al += a * a;
+        be += b * b;
+        ga += a * b;
+    }
+    al = group_allsum<GS>(al);
+    be = group_allsum<GS>(be);
+    ga = group_allsum<GS>(ga);
+    if (!(fabs(ga) > tol * sqrt(al * be)) || !(fabs(ga) > atol * sqrt(al > be ? al : be))) return false;
+    const T ze = (be - al) / ((T)2 * ga);
+    const T tt = (ze >= (T)0 ? (T)1 : (T)-1) / (fabs(ze) + sqrt((T)1 + ze * ze));
+    const T cc = (T)1 / sqrt((T)1 + tt * tt), ss = cc * tt;
+    for (int i = gl; i < N; i += GS) {
+        const T a = gp[i], b = gq[i];
+        gp[i] = cc * a - ss * b;
+        gq[i] = ss * a + cc * b;
+        const T c = vp[i], d = vq[i];
+        vp[i] = cc * c - ss * d;
+        vq[i] = ss * c + cc * d;
+    }
+    return true;
+}
+
 // Projects one block: the lower triangle of W is read from vs, the lower triangle of
-// P_{S+}(W) is written to us and v = u - w back to vs.  Cyclic two-sided Jacobi with round-robin parallel ordering;
-// A and V are N x N row-major with leading dimension ld (global scratch of this workgroup).
+// P_{S+}(W) is written to us and v = u - w back to vs.
+// P_{S+}(W) = (W + |W|) / 2 with |W| = V Sigma V^T: one-sided (Hestenes) Jacobi makes the
+// columns of G = W V mutually orthogonal by plane rotations applied to G and V alike;
+// then V holds eigenvectors of W and Sigma = diag(|g_j|) = |eigenvalues| (for a symmetric W
+// the right singular vectors are eigenvectors, and the formula holds within any group of
+// equal |lambda|).  Round-robin parallel ordering, one wavefront per column pair, one
+// barrier per round.  With a cached V from the previous ADMM iteration (warm) the sweeps
+// start from G = W V, which is nearly orthogonal once the iterates settle.
+// G, V: column-major N x N (column j at j*ld), in LDS or global scratch; Tm: N x N global.
 template <typename T, int NT>
-__device__ void project_block(T *__restrict__ vs, T *__restrict__ us, int N, T *__restrict__ A,
-                              T *__restrict__ V, int ld, T *s_rot, int *s_flag, double *s_red, int max_sweeps) {
-    const int tid = threadIdx.x;
+__device__ void project_block(T *__restrict__ vs, T *__restrict__ us, int N, T *__restrict__ Vs, bool warm,
+                              T *__restrict__ G, T *__restrict__ V, int ld, T *__restrict__ Tm, T *s_sig,
+                              const EigScratch &sc, int max_sweeps) {
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr int NW = NT / 64;
     if (N == 1) {
         if (tid == 0) {
             const T w = vs[0];
             const T x = w > (T)0 ? w : (T)0;
             us[0] = x;
             vs[0] = x - w;
+            if (Vs) Vs[0] = (T)1;
         }
         __syncthreads();
         return;
     }
+    // G = W (cold, V = I) or G = W V_prev (warm); W is symmetric, so column j of W = row j
     double fro2 = 0.0, dummy = 0.0;
     for (int idx = tid; idx < N * N; idx += NT) {
-        const int i = idx / N, j = idx - (idx / N) * N;
+        const int j = idx / N, i = idx - (idx / N) * N;   // column j, row i
         const int a = i > j ? i : j, bb = i > j ? j : i;
         const T x = vs[svec_idx(a, bb, N)];
-        A[i * ld + j] = x;
-        V[i * ld + j] = (i == j) ? (T)1 : (T)0;
         fro2 += (double)x * (double)x;
+        if (warm) {
+            Tm[j * N + i] = x;
+            V[j * ld + i] = Vs[j * N + i];
+        } else {
+            G[j * ld + i] = x;
+            V[j * ld + i] = (i == j) ? (T)1 : (T)0;
+        }
     }
-    block_sum2<NT>(fro2, dummy, s_red);
-    const T thresh = (T)(TS<T>::eps * sqrt(fro2) / (double)N);
+    __syncthreads();
+    if (warm) {
+        // G[:, j] = sum_k W[:, k] V[k, j]  (column-major: G^T = V^T W^T, computed as (V^T W)^T)
+        const int nt = (N + 3) >> 2;
+        for (int t = tid; t < nt * nt; t += NT) {
+            const int i0 = (t / nt) * 4, j0 = (t - (t / nt) * nt) * 4;
+            T acc[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+            for (int kk = 0; kk < N; ++kk) {
+                T wa[4], vb[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) wa[a] = (i0 + a < N) ? Tm[kk * N + i0 + a] : (T)0;   // W[i][k]
+#pragma unroll
+                for (int b = 0; b < 4; ++b) vb[b] = (j0 + b < N) ? V[(j0 + b) * ld + kk] : (T)0;   // V[k][j]
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] += wa[a] * vb[b];
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (i0 + a < N && j0 + b < N) G[(j0 + b) * ld + i0 + a] = acc[a][b];
+        }
+        __syncthreads();
+    }
+    block_sum2<NT>(fro2, dummy, sc.s_red);
+    // a pair is rotated while it is coupled beyond rounding, relative to both columns
+    // (16 eps) and absolutely (eps |W|_F times the larger column): below that, the pair's
+    // contribution to |W| is under the rounding error of W itself, and columns of
+    // near-zero eigenvalues stop trading noise
+    const T tol = (T)(16.0 * TS<T>::eps);
+    const T atol = (T)(TS<T>::eps * sqrt(fro2));
     const int M = N + (N & 1);
     const int H = M / 2;
-    T *s_c = s_rot, *s_s = s_rot + H, *s_t = s_rot + 2 * H, *s_app = s_rot + 3 * H, *s_aqq = s_rot + 4 * H,
-      *s_apq = s_rot + 5 * H;
-
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        if (tid == 0) *s_flag = 0;
+        if (tid == 0) *sc.s_flag = 0;
         __syncthreads();
+        int rotated = 0;
+        constexpr int GS = 16;                       // lanes per column pair
+        const int grp = tid / GS;
         for (int r = 0; r < M - 1; ++r) {
-            for (int kk = tid; kk < H; kk += NT) {
+            for (int kk = grp; kk < H; kk += NT / GS) {
                 int p, q;
                 rr_pair(r, kk, M, p, q);
-                T cc = (T)1, ss = (T)0, tt = (T)0, app = 0, aqq = 0, apq = 0;
-                if (q < N) {
-                    app = A[p * ld + p];
-                    aqq = A[q * ld + q];
-                    apq = A[p * ld + q];
-                    if (fabs(apq) > thresh) {
-                        const T th = (aqq - app) / ((T)2 * apq);
-                        const T sg = th >= (T)0 ? (T)1 : (T)-1;
-                        tt = sg / (fabs(th) + sqrt((T)1 + th * th));
-                        cc = (T)1 / sqrt((T)1 + tt * tt);
-                        ss = tt * cc;
-                        *s_flag = 1;
-                    }
-                }
-                s_c[kk] = cc;
-                s_s[kk] = ss;
-                s_t[kk] = tt;
-                s_app[kk] = app;
-                s_aqq[kk] = aqq;
-                s_apq[kk] = apq;
-            }
-            __syncthreads();
-            // A <- A J, V <- V J  (rotate column pairs)
-            for (int it = tid; it < N * H; it += NT) {
-                const int i = it / H, kk = it - (it / H) * H;
-                const T ss = s_s[kk];
-                if (ss == (T)0) continue;
-                const T cc = s_c[kk];
-                int p, q;
-                rr_pair(r, kk, M, p, q);
-                const T aip = A[i * ld + p], aiq = A[i * ld + q];
-                A[i * ld + p] = cc * aip - ss * aiq;
-                A[i * ld + q] = ss * aip + cc * aiq;
-                const T vip = V[i * ld + p], viq = V[i * ld + q];
-                V[i * ld + p] = cc * vip - ss * viq;
-                V[i * ld + q] = ss * vip + cc * viq;
-            }
-            __syncthreads();
-            // A <- J^T A  (rotate row pairs)
-            for (int it = tid; it < N * H; it += NT) {
-                const int kk = it / N, j = it - (it / N) * N;
-                const T ss = s_s[kk];
-                if (ss == (T)0) continue;
-                const T cc = s_c[kk];
-                int p, q;
-                rr_pair(r, kk, M, p, q);
-                const T apj = A[p * ld + j], aqj = A[q * ld + j];
-                A[p * ld + j] = cc * apj - ss * aqj;
-                A[q * ld + j] = ss * apj + cc * aqj;
-            }
-            __syncthreads();
-            // exact 2x2 results for the rotated pairs
-            for (int kk = tid; kk < H; kk += NT) {
-                if (s_s[kk] == (T)0) continue;
-                int p, q;
-                rr_pair(r, kk, M, p, q);
-                const T tt = s_t[kk], apq = s_apq[kk];
-                A[p * ld + p] = s_app[kk] - tt * apq;
-                A[q * ld + q] = s_aqq[kk] + tt * apq;
-                A[p * ld + q] = (T)0;
-                A[q * ld + p] = (T)0;
+                if (q < N && os_rotate_pair<T, GS>(G, ld, V, ld, N, p, q, tol, atol)) rotated = 1;
             }
             __syncthreads();
         }
-        const int any = *s_flag;
+        if (rotated) *sc.s_flag = 1;
         __syncthreads();
+        const int any = *sc.s_flag;
+        __syncthreads();
+        if (tid == 0) *sc.s_sweeps += 1;
         if (!any) break;
     }
-    // rebuild X = V max(L, 0) V^T over the lower triangle; u = X, v = u - w
-    const int nsv = N * (N + 1) / 2;
-    for (int s = tid; s < nsv; s += NT) {
-        // invert svec index: column j, row i >= j
-        int j = 0, rem = s;
-        while (rem >= N - j) {
-            rem -= N - j;
-            ++j;
-        }
-        const int i = j + rem;
-        T acc = (T)0;
-        for (int kk = 0; kk < N; ++kk) {
-            const T lam = A[kk * ld + kk];
-            if (lam > (T)0) acc += V[i * ld + kk] * lam * V[j * ld + kk];
-        }
-        const T x = acc;
-        const T w = vs[s];
-        us[s] = x;
-        vs[s] = x - w;
+    // sigma_j = |g_j|
+    for (int j = wid; j < N; j += NW) {
+        T s = 0;
+        for (int i = lane; i < N; i += 64) s += G[j * ld + i] * G[j * ld + i];
+        s = wave_allsum(s);
+        if (lane == 0) s_sig[j] = sqrt(s);
     }
+    __syncthreads();
+    // u = lower((W + V Sigma V^T) / 2), v = u - w, by 4 x 4 tiles on and below the diagonal
+    const int nt = (N + 3) >> 2;
+    const int ntri = nt * (nt + 1) / 2;
+    for (int t = tid; t < ntri; t += NT) {
+        int ta = 0, rem = t;
+        while (rem > ta) {
+            rem -= ta + 1;
+            ++ta;
+        }
+        const int a0 = ta * 4, b0 = rem * 4;   // tile row ta >= tile column rem
+        T acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+        for (int j = 0; j < N; ++j) {
+            const T sg = s_sig[j];
+            T va[4], vb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) va[a] = (a0 + a < N) ? V[j * ld + a0 + a] * sg : (T)0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) vb[b] = (b0 + b < N) ? V[j * ld + b0 + b] : (T)0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] += va[a] * vb[b];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = a0 + a, j = b0 + b;
+                if (i < N && j <= i) {
+                    const int s = svec_idx(i, j, N);
+                    const T w = vs[s];
+                    const T x = (T)0.5 * (w + acc[a][b]);
+                    us[s] = x;
+                    vs[s] = x - w;
+                }
+            }
+    }
+    if (Vs)
+        for (int idx = tid; idx < N * N; idx += NT) {
+            const int j = idx / N, i = idx - (idx / N) * N;
+            Vs[j * N + i] = V[j * ld + i];
+        }
     __syncthreads();
 }
 
@@ -487,13 +612,18 @@ template <typename T, int NT>
 __global__ __launch_bounds__(NT) void admm_persistent(RunParams rp) {
     __shared__ int s_idx;
     __shared__ int s_flag;
+    __shared__ int s_sweeps;
     __shared__ double s_red[4 * (NT / 64)];
     __shared__ double s_z[SOS_KMAX_LDS];
     extern __shared__ char dyn_lds[];
-    T *s_rot = reinterpret_cast<T *>(dyn_lds);
+    // dynamic LDS: sigma (eig_ld values), then G and V of blocks with N <= rp.lds_nmax,
+    // or G alone for blocks with N <= rp.lds_nmax_g
+    T *s_sig = reinterpret_cast<T *>(dyn_lds);
+    T *s_mat = reinterpret_cast<T *>(dyn_lds + rp.lds_mat_off);
 
     char *wbase = reinterpret_cast<char *>(rp.work) + (long long)blockIdx.x * rp.work_stride;
     char *ebase = reinterpret_cast<char *>(rp.eig) + (long long)blockIdx.x * rp.eig_stride;
+    EigScratch sc{&s_flag, &s_sweeps, s_red};
 
     for (;;) {
         if (threadIdx.x == 0) s_idx = atomicAdd(rp.counter, 1);
@@ -505,20 +635,38 @@ __global__ __launch_bounds__(NT) void admm_persistent(RunParams rp) {
         const ProbDesc &P = rp.probs[pid];
         T *wy = reinterpret_cast<T *>(wbase);
         T *wx = wy + ((P.m + 63) & ~63);
-        T *EA = reinterpret_cast<T *>(ebase);
-        T *EV = EA + (long long)rp.eig_ld * P.nmax;
+        T *Tm = reinterpret_cast<T *>(ebase);
         T *u = TS<T>::u(P);
         T *v = TS<T>::v(P);
+        T *vstore = TS<T>::vstore(P);
+        bool warm = P.tk[2] != 0.0;
+        if (threadIdx.x == 0) s_sweeps = 0;
 
         int it = 0;
         int status = 0;
         while (it < rp.iters) {
             affine_phase<T, NT>(P, rp, wy, wx, s_z, s_red);
+            long long voff = 0;
             for (int bk = 0; bk < P.nblk; ++bk) {
                 const int off = P.blk_off[bk];
-                project_block<T, NT>(v + off, u + off, P.blk_N[bk], EA, EV, rp.eig_ld, s_rot, &s_flag, s_red,
-                                     rp.max_sweeps);
+                const int N = P.blk_N[bk];
+                T *EG, *EV;
+                const int ld = N;
+                if (N <= rp.lds_nmax) {
+                    EG = s_mat;
+                    EV = s_mat + (long long)N * N;
+                } else if (N <= rp.lds_nmax_g) {
+                    EG = s_mat;
+                    EV = Tm + (long long)P.nmax * P.nmax;
+                } else {
+                    EG = Tm + (long long)P.nmax * P.nmax;
+                    EV = EG + (long long)P.nmax * P.nmax;
+                }
+                project_block<T, NT>(v + off, u + off, N, rp.warm_eig ? vstore + voff : nullptr,
+                                     rp.warm_eig && warm, EG, EV, ld, Tm, s_sig, sc, rp.max_sweeps);
+                voff += (long long)N * N;
             }
+            warm = rp.warm_eig != 0;
             ++it;
             if (rp.mode == RUN_SOLVE && it >= rp.min_iters && (it % rp.check_every == 0 || it == rp.iters)) {
                 status = residual_phase<T, NT>(P, rp.tol, s_red, it);
@@ -529,7 +677,11 @@ __global__ __launch_bounds__(NT) void admm_persistent(RunParams rp) {
             status = residual_phase<T, NT>(P, rp.tol, s_red, it);
             if (rp.mode == RUN_SOLVE && status == 0 && threadIdx.x == 0) P.out[SOS_OUT_STATUS] = 4;
         }
-        if (threadIdx.x == 0) P.out[SOS_OUT_TOTAL] = (rp.accumulate ? P.out[SOS_OUT_TOTAL] : 0.0) + it;
+        if (threadIdx.x == 0) {
+            P.out[SOS_OUT_SWEEPS] = (it > 0 && P.nblk > 0) ? (double)s_sweeps / ((double)it * P.nblk) : 0.0;
+            P.out[SOS_OUT_TOTAL] = (rp.accumulate ? P.out[SOS_OUT_TOTAL] : 0.0) + it;
+            if (it > 0) P.tk[2] = rp.warm_eig ? 1.0 : 0.0;
+        }
         __syncthreads();
     }
 }
@@ -553,6 +705,7 @@ __global__ void cast_state(const ProbDesc *probs, const int *ids, int count, int
             if (i < nv) P.v32[i] = (float)P.v64[i];
         }
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) P.tk[2] = 0.0;   // the other precision's eigenvectors are stale
 }
 
 // cold start u = v = (0, 0, 1) for every listed problem (both precisions)
@@ -572,13 +725,37 @@ __global__ void reset_state(const ProbDesc *probs, int count) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         P.tk[0] = 1.0;
         P.tk[1] = 1.0;
+        P.tk[2] = 0.0;
     }
 }
 
+// Dynamic LDS layout for element type T: sigma, then G and V (both N x N) for blocks up to
+// lds_nmax, or G alone for blocks up to lds_nmax_g; larger blocks work in global scratch.
+template <typename T>
+void lds_layout(int eig_ld, int lds_budget, int &mat_off, int &lds_nmax, int &lds_nmax_g, size_t &bytes) {
+    size_t off = sizeof(T) * (size_t)(eig_ld + 1);
+    off = (off + 15) & ~(size_t)15;
+    mat_off = (int)off;
+    lds_nmax = lds_nmax_g = 0;
+    for (int N = eig_ld; N >= 2 && !lds_nmax; --N)
+        if ((long long)(off + sizeof(T) * 2 * (size_t)N * N) <= lds_budget) lds_nmax = N;
+    for (int N = eig_ld; N >= 2 && !lds_nmax_g; --N)
+        if ((long long)(off + sizeof(T) * (size_t)N * N) <= lds_budget) lds_nmax_g = N;
+    const size_t need2 = lds_nmax ? off + sizeof(T) * 2 * (size_t)lds_nmax * lds_nmax : off;
+    const size_t need1 = lds_nmax_g ? off + sizeof(T) * (size_t)lds_nmax_g * lds_nmax_g : off;
+    bytes = need2 > need1 ? need2 : need1;
+}
+
 template <typename T, int NT>
-int launch_t(int grid, const RunParams &rp, hipStream_t st) {
-    const int H = (rp.eig_ld + 2) / 2;
-    const size_t lds = sizeof(T) * 6 * (size_t)H;
+int launch_t(int grid, const RunParams &rp_in, hipStream_t st) {
+    RunParams rp = rp_in;
+    size_t lds = 0;
+    lds_layout<T>(rp.eig_ld, rp.lds_budget, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds);
+    if (lds > 64 * 1024) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&admm_persistent<T, NT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();   // not every runtime needs (or accepts during capture) the attribute
+    }
     hipLaunchKernelGGL((admm_persistent<T, NT>), dim3(grid), dim3(NT), lds, st, rp);
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
@@ -608,6 +785,7 @@ int sos_launch_admm(int fp64, int threads, int grid, const RunParams &rp, void *
 }
 
 int sos_launch_reset(int *counter, void *stream) {
+    (void)hipGetLastError();
     hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), counter);
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
@@ -618,6 +796,7 @@ int sos_launch_cast_state(const ProbDesc *probs_dev, const int *ids, int count, 
     int gx = (max_len + 255) / 256;
     if (gx > 64) gx = 64;
     if (gx < 1) gx = 1;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(cast_state, dim3(gx, count), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), probs_dev,
                        ids, count, to64);
     return hipGetLastError() == hipSuccess ? 0 : -4;
@@ -628,6 +807,7 @@ int sos_launch_reset_state(const ProbDesc *probs_dev, int count, int max_len, vo
     int gx = (max_len + 255) / 256;
     if (gx > 64) gx = 64;
     if (gx < 1) gx = 1;
+    (void)hipGetLastError();
     hipLaunchKernelGGL(reset_state, dim3(gx, count), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), probs_dev,
                        count);
     return hipGetLastError() == hipSuccess ? 0 : -4;
