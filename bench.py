@@ -36,10 +36,18 @@ def workload_pop_batch(count: int):
     return [F.pop_batch_member(s) for s in range(count)]
 
 
+def workload_lyapunov_test(count: int):
+    from sosgen import families as F
+    return [F.lyapunov(s) for s in range(3584, 3584 + count)]
+
+
 WORKLOADS = {
-    "pop_batch_512": dict(make=lambda: workload_pop_batch(512), count=512,
+    "pop_batch_512": dict(make=lambda: workload_pop_batch(512), count=512, plain_sample=4,
                           desc="512 unconstrained quartic POPs, n ~ U{6..16} (Gram 28..153, m 210..4845), "
-                               "seeds 0..511, batched FP32 bulk + FP64 polish, cold start"),
+                               "seeds 0..511, variables scaled, batched FP32 bulk + FP64 polish, cold start"),
+    "lyapunov_512": dict(make=lambda: workload_lyapunov_test(512), count=512, plain_sample=32,
+                         desc="512 Lyapunov programs, n = 6, quartic V (t = 203 free, Gram 28 and 84, m = 1134), "
+                              "seeds 3584..4095, batched FP32 bulk + FP64 polish, cold start"),
 }
 
 
@@ -85,10 +93,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="pop_batch_512", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="lyapunov_512", choices=sorted(WORKLOADS))
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--schedule", default=None, help="schedule JSON string or file")
-    ap.add_argument("--plain-sample", type=int, default=16)
+    ap.add_argument("--plain-sample", type=int, default=0, help="0 = the workload's default")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -170,7 +178,8 @@ def main():
     # plain FP64 arm: one problem at a time, every step in FP64, cold start
     plain = None
     if not args.no_plain:
-        idx = np.linspace(0, len(probs) - 1, args.plain_sample).astype(int)
+        ns = args.plain_sample or wl["plain_sample"]
+        idx = np.linspace(0, len(probs) - 1, ns).astype(int)
         s64 = B.sos_default_settings(tol=args.tol, max_iters=2000, check_every=10, precision=B.SOS_FP64)
         tms, ok64 = 0.0, 0
         for i in idx:

@@ -185,6 +185,46 @@ double sos_batch_phase_ms(const sos_batch *b, int32_t phase);
 
 void sos_batch_free(sos_batch *b);
 
+/* ---------------------------------------------------------------- learned warm start
+   The library's own iterate layout, used by the two calls below: per problem one row of
+   nx + m values, [xi (nx) | y (m)], where xi lists the free variables and then the lower
+   triangle (by columns, unscaled) of every PSD block.  sos_layout_size gives nx + m. */
+int64_t sos_layout_size(const sos_work *w);
+
+/* For every problem p of the batch, from the predicted row pred_dev + p * ld (device,
+   FP32, layout above) sets u = (P_K(xi), y, 1) and v = (P_K*(c - A^T y), 0, 0): the
+   prediction made consistent with the cones, with tau = 1, kappa = 0.  One device kernel
+   on the batch's stream; the next sos_batch_solve starts from it. */
+int sos_batch_warm_start(sos_batch *b, const float *pred_dev, int64_t ld);
+
+/* Writes [xi / tau | y / tau] of every problem (FP64 iterate after a solve) as FP32 rows
+   of length >= nx + m, ld apart, into out_dev (device).  Rows of problems with tau = 0
+   (certificates) are zero. */
+int sos_batch_export_solutions(sos_batch *b, float *out_dev, int64_t ld);
+
+/* A small FP32 multilayer perceptron, input -> H -> H -> output with GELU (the exact,
+   erf form) after both hidden layers, trained with mean squared error and Adam on the
+   device.  Parameters form one buffer [W1 (in x H) | b1 | W2 (H x H) | b2 | W3 (H x out) | b3],
+   row-major, a layer being Z = X W + b for row-major batches.  All X, T, Y pointers are
+   device pointers to row-major FP32 batches of at most max_batch rows.  Work is ordered
+   on hip_stream. */
+typedef struct sos_mlp sos_mlp;
+int sos_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t max_batch, void *hip_stream,
+                   sos_mlp **out);
+int64_t sos_mlp_num_params(const sos_mlp *m);
+/* host_params: sos_mlp_num_params floats; also resets the Adam state */
+int sos_mlp_set_params(sos_mlp *m, const float *host_params);
+int sos_mlp_get_params(const sos_mlp *m, float *host_params);
+/* Y <- Y * scale + shift per output column, applied by sos_mlp_forward when asked */
+int sos_mlp_set_output_affine(sos_mlp *m, const float *host_scale, const float *host_shift);
+int sos_mlp_forward(sos_mlp *m, const float *X_dev, int32_t batch, float *Y_dev, int32_t apply_output_affine);
+/* gradient of mean((Y - T)^2) w.r.t. every parameter into grad_host (num_params floats), loss into loss_host */
+int sos_mlp_gradient(sos_mlp *m, const float *X_dev, const float *T_dev, int32_t batch, float *grad_host,
+                     double *loss_host);
+/* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on mean((Y - T)^2); loss_host may be NULL */
+int sos_mlp_train_step(sos_mlp *m, const float *X_dev, const float *T_dev, int32_t batch, float lr, double *loss_host);
+void sos_mlp_free(sos_mlp *m);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,10 @@ STATUS_NAMES = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_inf
 EXPORTED = ["sos_default_settings", "sos_setup", "sos_step", "sos_solve", "sos_warm_start",
             "sos_get_solution", "sos_get_iterate", "sos_set_iterate", "sos_last_error", "sos_free",
             "sos_batch_setup", "sos_batch_solve", "sos_batch_reset", "sos_batch_last_ms",
-            "sos_batch_phase_ms", "sos_batch_free"]
+            "sos_batch_phase_ms", "sos_batch_free", "sos_layout_size", "sos_batch_warm_start",
+            "sos_batch_export_solutions", "sos_mlp_create", "sos_mlp_num_params", "sos_mlp_set_params",
+            "sos_mlp_get_params", "sos_mlp_set_output_affine", "sos_mlp_forward", "sos_mlp_gradient",
+            "sos_mlp_train_step", "sos_mlp_free"]
 
 
 class SosError(RuntimeError):
@@ -101,8 +104,25 @@ def load():
     lib.sos_batch_phase_ms.restype = C.c_double
     lib.sos_batch_free.argtypes = [vp]
     lib.sos_batch_free.restype = None
+    fp = P(C.c_float)
+    lib.sos_layout_size.argtypes = [vp]
+    lib.sos_layout_size.restype = C.c_int64
+    lib.sos_batch_warm_start.argtypes = [vp, vp, C.c_int64]
+    lib.sos_batch_export_solutions.argtypes = [vp, vp, C.c_int64]
+    lib.sos_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, P(vp)]
+    lib.sos_mlp_num_params.argtypes = [vp]
+    lib.sos_mlp_num_params.restype = C.c_int64
+    lib.sos_mlp_set_params.argtypes = [vp, fp]
+    lib.sos_mlp_get_params.argtypes = [vp, fp]
+    lib.sos_mlp_set_output_affine.argtypes = [vp, fp, fp]
+    lib.sos_mlp_forward.argtypes = [vp, vp, C.c_int32, vp, C.c_int32]
+    lib.sos_mlp_gradient.argtypes = [vp, vp, vp, C.c_int32, fp, P(C.c_double)]
+    lib.sos_mlp_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, P(C.c_double)]
+    lib.sos_mlp_free.argtypes = [vp]
+    lib.sos_mlp_free.restype = None
     for name in EXPORTED:
-        if name not in ("sos_free", "sos_batch_free", "sos_last_error", "sos_batch_last_ms", "sos_batch_phase_ms"):
+        if name not in ("sos_free", "sos_batch_free", "sos_last_error", "sos_batch_last_ms", "sos_batch_phase_ms",
+                        "sos_layout_size", "sos_mlp_num_params", "sos_mlp_free"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -278,3 +298,79 @@ def sos_batch_phase_ms(batch: Batch, phase: int) -> float:
 
 def sos_batch_free(batch: Batch) -> None:
     batch.free()
+
+
+# ---------------------------------------------------------------- learned warm start
+def _dev(t):
+    """Device pointer of a contiguous float32 cuda tensor."""
+    import torch
+    assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+def sos_layout_size(w: Work) -> int:
+    return int(load().sos_layout_size(w.handle))
+
+
+def sos_batch_warm_start(batch: Batch, pred, ld: int) -> None:
+    """pred: cuda float32 tensor with one row of >= nx + m values per problem, ld apart."""
+    _check(load().sos_batch_warm_start(batch.handle, _dev(pred), int(ld)), None)
+
+
+def sos_batch_export_solutions(batch: Batch, out, ld: int) -> None:
+    _check(load().sos_batch_export_solutions(batch.handle, _dev(out), int(ld)), None)
+
+
+class MLP:
+    """Handle of the device MLP (all compute in the library's kernels)."""
+
+    def __init__(self, n_in: int, n_hidden: int, n_out: int, max_batch: int, stream=None):
+        self.n_in, self.n_hidden, self.n_out, self.max_batch = n_in, n_hidden, n_out, max_batch
+        h = C.c_void_p()
+        st = stream if stream is not None else current_stream()
+        _check(load().sos_mlp_create(n_in, n_hidden, n_out, max_batch, st, C.byref(h)), None)
+        self.handle = h
+        self.num_params = int(load().sos_mlp_num_params(h))
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def free(self):
+        if getattr(self, "handle", None):
+            load().sos_mlp_free(self.handle)
+            self.handle = None
+
+    def set_params(self, params: np.ndarray) -> None:
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.shape == (self.num_params,)
+        _check(load().sos_mlp_set_params(self.handle, p.ctypes.data_as(C.POINTER(C.c_float))), None)
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(self.num_params, dtype=np.float32)
+        _check(load().sos_mlp_get_params(self.handle, p.ctypes.data_as(C.POINTER(C.c_float))), None)
+        return p
+
+    def set_output_affine(self, scale: np.ndarray, shift: np.ndarray) -> None:
+        s = np.ascontiguousarray(scale, dtype=np.float32)
+        t = np.ascontiguousarray(shift, dtype=np.float32)
+        _check(load().sos_mlp_set_output_affine(self.handle, s.ctypes.data_as(C.POINTER(C.c_float)),
+                                                t.ctypes.data_as(C.POINTER(C.c_float))), None)
+
+    def forward(self, X, Y, apply_output_affine: bool = False) -> None:
+        _check(load().sos_mlp_forward(self.handle, _dev(X), X.shape[0], _dev(Y), int(apply_output_affine)), None)
+
+    def gradient(self, X, T):
+        g = np.empty(self.num_params, dtype=np.float32)
+        loss = C.c_double()
+        _check(load().sos_mlp_gradient(self.handle, _dev(X), _dev(T), X.shape[0],
+                                       g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss)), None)
+        return g, loss.value
+
+    def train_step(self, X, T, lr: float, want_loss: bool = False):
+        loss = C.c_double()
+        _check(load().sos_mlp_train_step(self.handle, _dev(X), _dev(T), X.shape[0], float(lr),
+                                         C.byref(loss) if want_loss else None), None)
+        return loss.value if want_loss else None

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsos.so")
-SOURCES = ["sos_kernels.hip", "sos_host.cpp"]
+SOURCES = ["sos_kernels.hip", "sos_mlp.hip", "sos_host.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",
          # packed FP32 instructions off for every device function
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

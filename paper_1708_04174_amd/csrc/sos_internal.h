@@ -83,12 +83,17 @@ struct RunParams {
     int warm_eig;           // start each block's Jacobi sweeps from the previous iteration's eigenvectors
     int lds_budget;         // dynamic LDS bytes the launch may use
     int lds_mat_off, lds_nmax, lds_nmax_g;   // filled in by the launcher
-    int accumulate;         // 0: out[TOTAL] = iterations of this launch; 1: out[TOTAL] += them
+    int accumulate;         // 0: out[TOTAL] = iterations of this launch; 1: out[TOTAL] += them, and the
+                            //    iteration budget is iters - out[TOTAL] (at least min_iters)
+    int stall_checks;       // > 0: stop a problem whose residual missed 0.9 x its best this many checks in a row
+    unsigned long long *ts; // optional [start, end] wall-clock stamps of the launch (min / max over workgroups)
 };
 
 // host-side launchers implemented in sos_kernels.hip
 int sos_launch_admm(int fp64, int threads, int grid, const RunParams &rp, void *stream);
-int sos_launch_reset(int *counter, void *stream);
+int sos_launch_reset(int *counter, void *stream, unsigned long long *ts = nullptr);
 int sos_launch_cast_state(const ProbDesc *probs_dev, const int *ids, int count, int to64, void *stream,
                           int max_len);
 int sos_launch_reset_state(const ProbDesc *probs_dev, int count, int max_len, void *stream);
+int sos_launch_warm_start(int fp64, int threads, const RunParams &rp, const float *pred, long long ld, void *stream);
+int sos_launch_export(int fp64, const ProbDesc *probs, int count, float *out, long long ld, int max_len, void *stream);

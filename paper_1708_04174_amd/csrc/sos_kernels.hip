@@ -135,8 +135,11 @@ __device__ void chol_solve_wave(const double *__restrict__ Lcol, const double *_
 }
 
 // ----------------------------------------------------------------------------- affine step
-template <typename T, int NT>
-__device__ void affine_phase(const ProbDesc &P, const RunParams &rp, T *__restrict__ wy, T *__restrict__ wx,
+// T: storage type of u, v, A, b, c, h; AT: the type the affine step computes and
+// accumulates in (the storage type; a variant with FP64 arithmetic on FP32 storage
+// left the FP32 residual floor unchanged, since the floor comes from the stored iterate).
+template <typename T, int NT, typename AT>
+__device__ void affine_phase(const ProbDesc &P, const RunParams &rp, AT *__restrict__ wy, AT *__restrict__ wx,
                              double *s_z, double *s_red) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     constexpr int NW = NT / 64;
@@ -158,18 +161,18 @@ __device__ void affine_phase(const ProbDesc &P, const RunParams &rp, T *__restri
 
     const double tau = P.tk[0], kap = P.tk[1];
     const double wtau = tau + kap;
-    const T wt = (T)wtau;
+    const AT wt = (AT)wtau;
     const T *__restrict__ uy = u + nx;
 
     // P1: x = (w2 - A w1) / d
     for (int a = tid; a < m; a += NT) {
-        T acc = uy[a] + b[a] * wt;
+        AT acc = (AT)uy[a] + (AT)b[a] * wt;
         const int e1 = rowptr[a + 1];
         for (int e = rowptr[a]; e < e1; ++e) {
             const int j = colidx[e];
-            acc -= val[e] * (u[j] + v[j] - c[j] * wt);
+            acc -= (AT)val[e] * ((AT)u[j] + (AT)v[j] - (AT)c[j] * wt);
         }
-        wy[a] = acc * dinv[a];
+        wy[a] = acc * (AT)dinv[a];
     }
     __syncthreads();
 
@@ -194,11 +197,11 @@ __device__ void affine_phase(const ProbDesc &P, const RunParams &rp, T *__restri
         const int *__restrict__ frptr = P.frptr;
         const int *__restrict__ frcol = P.frcol;
         for (int a = tid; a < m; a += NT) {
-            T s2 = wy[a];
+            AT s2 = wy[a];
             if (k > 0) {
                 double acc = 0.0;
                 for (int e = frptr[a]; e < frptr[a + 1]; ++e) acc += (double)frval[e] * s_z[frcol[e]];
-                s2 = s2 - (T)(acc * (double)dinv[a]);
+                s2 = s2 - (AT)(acc * (double)dinv[a]);
             }
             wy[a] = s2;
             bs += (double)b[a] * (double)s2;
@@ -212,15 +215,15 @@ __device__ void affine_phase(const ProbDesc &P, const RunParams &rp, T *__restri
         const int *__restrict__ fptr = P.fptr;
         const int *__restrict__ frow = P.frow;
         for (int e = tid; e < nx; e += NT) {
-            const T w1 = u[e] + v[e] - c[e] * wt;
+            const AT w1 = (AT)u[e] + (AT)v[e] - (AT)c[e] * wt;
             const int r = colrow[e];
-            T s1 = w1;
+            AT s1 = w1;
             if (r >= 0) {
-                s1 = w1 + colval[e] * wy[r];
+                s1 = w1 + (AT)colval[e] * wy[r];
             } else if (r <= -2) {
                 const int j = -2 - r;
-                T acc = (T)0;
-                for (int i = fptr[j]; i < fptr[j + 1]; ++i) acc += fval[i] * wy[frow[i]];
+                AT acc = (AT)0;
+                for (int i = fptr[j]; i < fptr[j + 1]; ++i) acc += (AT)fval[i] * wy[frow[i]];
                 s1 = w1 + acc;
             }
             wx[e] = s1;
@@ -229,26 +232,26 @@ __device__ void affine_phase(const ProbDesc &P, const RunParams &rp, T *__restri
     }
     block_sum2<NT>(cs, bs, s_red);
     const double theta = (cs - bs) / P.eta;
-    const T th = (T)theta;
-    const T al = (T)rp.alpha;
+    const AT th = (AT)theta;
+    const AT al = (AT)rp.alpha;
     const bool relax = rp.alpha != 1.0;
 
     // P5: u_hat, w = u_hat - v, direct updates of the free, y and tau parts
     for (int e = tid; e < nx; e += NT) {
-        T uh = wx[e] - th * h[e];
-        if (relax) uh = al * uh + ((T)1 - al) * u[e];
-        const T w = uh - v[e];
+        AT uh = wx[e] - th * (AT)h[e];
+        if (relax) uh = al * uh + ((AT)1 - al) * (AT)u[e];
+        const AT w = uh - (AT)v[e];
         if (e < nfree) {
-            u[e] = w;
+            u[e] = (T)w;
             v[e] = (T)0;
         } else {
-            v[e] = w;   // parked for the PSD projection
+            v[e] = (T)w;   // parked for the PSD projection
         }
     }
     for (int a = tid; a < m; a += NT) {
-        T uh = wy[a] - th * h[nx + a];
-        if (relax) uh = al * uh + ((T)1 - al) * u[nx + a];
-        u[nx + a] = uh;
+        AT uh = wy[a] - th * (AT)h[nx + a];
+        if (relax) uh = al * uh + ((AT)1 - al) * (AT)u[nx + a];
+        u[nx + a] = (T)uh;
     }
     if (tid == 0) {
         double uht = wtau + theta;
@@ -537,7 +540,7 @@ __device__ void project_block(T *__restrict__ vs, T *__restrict__ us, int N, T *
 
 // ----------------------------------------------------------------------------- residuals (FP64)
 template <typename T, int NT>
-__device__ int residual_phase(const ProbDesc &P, double tol, double *s_red, int iters_done) {
+__device__ int residual_phase(const ProbDesc &P, double tol, double *s_red, int iters_done, double *res_max = nullptr) {
     const int tid = threadIdx.x;
     const int m = P.m, nx = P.nx;
     const T *__restrict__ u = TS<T>::u(P);
@@ -586,6 +589,7 @@ __device__ int residual_phase(const ProbDesc &P, double tol, double *s_red, int 
         dobj = by / tau;
     }
     const double mx = fmax(rpn, fmax(rdn, gap));
+    if (res_max) *res_max = mx;
     if (mx <= tol) status = 1;
     else if (by > 0.0 && sqrt(saty) <= tol * by) status = 2;
     else if (cx < 0.0 && sqrt(sax) <= tol * (-cx)) status = 3;
@@ -624,6 +628,7 @@ __global__ __launch_bounds__(NT) void admm_persistent(RunParams rp) {
     char *wbase = reinterpret_cast<char *>(rp.work) + (long long)blockIdx.x * rp.work_stride;
     char *ebase = reinterpret_cast<char *>(rp.eig) + (long long)blockIdx.x * rp.eig_stride;
     EigScratch sc{&s_flag, &s_sweeps, s_red};
+    if (rp.ts && threadIdx.x == 0) atomicMin(&rp.ts[0], (unsigned long long)wall_clock64());
 
     for (;;) {
         if (threadIdx.x == 0) s_idx = atomicAdd(rp.counter, 1);
@@ -644,8 +649,17 @@ __global__ __launch_bounds__(NT) void admm_persistent(RunParams rp) {
 
         int it = 0;
         int status = 0;
-        while (it < rp.iters) {
-            affine_phase<T, NT>(P, rp, wy, wx, s_z, s_red);
+        // iteration budget: in an accumulating (second) phase, what the first phase left over
+        int cap = rp.iters;
+        if (rp.accumulate) {
+            cap = rp.iters - (int)P.out[SOS_OUT_TOTAL];
+            if (cap < rp.min_iters) cap = rp.min_iters;
+        }
+        double best = INFINITY;
+        int since_best = 0;
+        bool stalled = false;
+        while (it < cap) {
+            affine_phase<T, NT, T>(P, rp, wy, wx, s_z, s_red);
             long long voff = 0;
             for (int bk = 0; bk < P.nblk; ++bk) {
                 const int off = P.blk_off[bk];
@@ -668,14 +682,26 @@ __global__ __launch_bounds__(NT) void admm_persistent(RunParams rp) {
             }
             warm = rp.warm_eig != 0;
             ++it;
-            if (rp.mode == RUN_SOLVE && it >= rp.min_iters && (it % rp.check_every == 0 || it == rp.iters)) {
-                status = residual_phase<T, NT>(P, rp.tol, s_red, it);
+            if (rp.mode == RUN_SOLVE && it >= rp.min_iters && (it % rp.check_every == 0 || it == cap)) {
+                double mx = INFINITY;
+                status = residual_phase<T, NT>(P, rp.tol, s_red, it, &mx);
                 if (status) break;
+                // a phase that stops improving hands over (the FP32 phase of the mixed form):
+                // stalled once stall_checks checks in a row missed 0.9 x the best residual
+                if (rp.stall_checks > 0) {
+                    if (mx < 0.9 * best) {
+                        best = mx;
+                        since_best = 0;
+                    } else if (++since_best >= rp.stall_checks) {
+                        stalled = true;
+                        break;
+                    }
+                }
             }
         }
         if (rp.mode == RUN_STEP || status == 0) {
             status = residual_phase<T, NT>(P, rp.tol, s_red, it);
-            if (rp.mode == RUN_SOLVE && status == 0 && threadIdx.x == 0) P.out[SOS_OUT_STATUS] = 4;
+            if (rp.mode == RUN_SOLVE && status == 0 && !stalled && threadIdx.x == 0) P.out[SOS_OUT_STATUS] = 4;
         }
         if (threadIdx.x == 0) {
             P.out[SOS_OUT_SWEEPS] = (it > 0 && P.nblk > 0) ? (double)s_sweeps / ((double)it * P.nblk) : 0.0;
@@ -684,10 +710,98 @@ __global__ __launch_bounds__(NT) void admm_persistent(RunParams rp) {
         }
         __syncthreads();
     }
+    if (rp.ts && threadIdx.x == 0) atomicMax(&rp.ts[1], (unsigned long long)wall_clock64());
 }
 
-__global__ void reset_counter(int *c) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
+// Learned warm start: from a predicted (xi, y) (FP32 rows, internal layout), set
+//   u = (P_K(xi), y, 1),  v = (P_{K*}(c - A^T y), 0, 0)
+// for every problem of a batch; one workgroup per problem.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void warm_start_kernel(RunParams rp, const float *__restrict__ pred, long long ld) {
+    __shared__ int s_flag;
+    __shared__ int s_sweeps;
+    __shared__ double s_red[4 * (NT / 64)];
+    extern __shared__ char dyn_lds[];
+    T *s_sig = reinterpret_cast<T *>(dyn_lds);
+    T *s_mat = reinterpret_cast<T *>(dyn_lds + rp.lds_mat_off);
+    const int p = blockIdx.x;
+    if (p >= rp.count) return;
+    const ProbDesc &P = rp.probs[p];
+    char *wbase = reinterpret_cast<char *>(rp.work) + (long long)blockIdx.x * rp.work_stride;
+    char *ebase = reinterpret_cast<char *>(rp.eig) + (long long)blockIdx.x * rp.eig_stride;
+    T *wx = reinterpret_cast<T *>(wbase);
+    T *Tm = reinterpret_cast<T *>(ebase);
+    EigScratch sc{&s_flag, &s_sweeps, s_red};
+    T *u = TS<T>::u(P);
+    T *v = TS<T>::v(P);
+    const float *xs = pred + (long long)p * ld;
+    const float *ys = xs + P.nx;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < P.m; i += NT) u[P.nx + i] = (T)ys[i];
+    for (int e = tid; e < P.nx; e += NT) {
+        u[e] = (T)xs[e];
+        double aty = 0.0;
+        const int r = P.colrow[e];
+        if (r >= 0) {
+            aty = P.colval64[e] * (double)ys[r];
+        } else if (r <= -2) {
+            const int j = -2 - r;
+            for (int i = P.fptr[j]; i < P.fptr[j + 1]; ++i) aty += P.fval64[i] * (double)ys[P.frow[i]];
+        }
+        v[e] = e < P.nfree ? (T)0 : (T)(P.c64[e] - aty);
+    }
+    __syncthreads();
+    for (int bk = 0; bk < P.nblk; ++bk) {
+        const int off = P.blk_off[bk];
+        const int N = P.blk_N[bk];
+        const int ns = N * (N + 1) / 2;
+        T *EG, *EV;
+        if (N <= rp.lds_nmax) {
+            EG = s_mat;
+            EV = s_mat + (long long)N * N;
+        } else if (N <= rp.lds_nmax_g) {
+            EG = s_mat;
+            EV = Tm + (long long)P.nmax * P.nmax;
+        } else {
+            EG = Tm + (long long)P.nmax * P.nmax;
+            EV = EG + (long long)P.nmax * P.nmax;
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+            T *blk = (pass == 0 ? u : v) + off;   // projected in place via the scratch wx
+            project_block<T, NT>(blk, wx, N, nullptr, false, EG, EV, N, Tm, s_sig, sc, rp.max_sweeps);
+            for (int s = tid; s < ns; s += NT) blk[s] = wx[s];
+            __syncthreads();
+        }
+    }
+    if (tid == 0) {
+        P.tk[0] = 1.0;
+        P.tk[1] = 0.0;
+        P.tk[2] = 0.0;
+    }
+}
+
+// rows of out (ld apart): [xi / tau (nx) | y / tau (m)] of every problem, FP32, internal layout
+template <typename T>
+__global__ void export_solution(const ProbDesc *probs, int count, float *out, long long ld) {
+    const int p = blockIdx.y;
+    if (p >= count) return;
+    const ProbDesc &P = probs[p];
+    const T *u = TS<T>::u(P);
+    const double tau = P.tk[0];
+    const double s = tau > 0.0 ? 1.0 / tau : 0.0;
+    const int n = P.nx + P.m;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        out[(long long)p * ld + i] = (float)((double)u[i] * s);
+}
+
+__global__ void reset_counter(int *c, unsigned long long *ts) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *c = 0;
+        if (ts) {
+            ts[0] = ~0ull;
+            ts[1] = 0ull;
+        }
+    }
 }
 
 // state conversion between the FP32 and FP64 copies of u and v
@@ -784,9 +898,9 @@ int sos_launch_admm(int fp64, int threads, int grid, const RunParams &rp, void *
     return -1;
 }
 
-int sos_launch_reset(int *counter, void *stream) {
+int sos_launch_reset(int *counter, void *stream, unsigned long long *ts) {
     (void)hipGetLastError();
-    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), counter);
+    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), counter, ts);
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
@@ -810,5 +924,44 @@ int sos_launch_reset_state(const ProbDesc *probs_dev, int count, int max_len, vo
     (void)hipGetLastError();
     hipLaunchKernelGGL(reset_state, dim3(gx, count), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), probs_dev,
                        count);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int sos_launch_warm_start(int fp64, int threads, const RunParams &rp_in, const float *pred, long long ld, void *stream) {
+    RunParams rp = rp_in;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    size_t lds = 0;
+    (void)hipGetLastError();
+#define SOS_WS(TT, NTT)                                                                                          \
+    {                                                                                                           \
+        lds_layout<TT>(rp.eig_ld, rp.lds_budget, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds);              \
+        if (lds > 64 * 1024) {                                                                                  \
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&warm_start_kernel<TT, NTT>),               \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                    \
+            (void)hipGetLastError();                                                                            \
+        }                                                                                                       \
+        hipLaunchKernelGGL((warm_start_kernel<TT, NTT>), dim3(rp.count), dim3(NTT), lds, st, rp, pred, ld);      \
+    }
+    if (fp64) {
+        if (threads == 256) SOS_WS(double, 256) else if (threads == 512) SOS_WS(double, 512) else if (threads == 128) SOS_WS(double, 128) else SOS_WS(double, 64)
+    } else {
+        if (threads == 256) SOS_WS(float, 256) else if (threads == 512) SOS_WS(float, 512) else if (threads == 128) SOS_WS(float, 128) else SOS_WS(float, 64)
+    }
+#undef SOS_WS
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int sos_launch_export(int fp64, const ProbDesc *probs, int count, float *out, long long ld, int max_len, void *stream) {
+    if (count <= 0) return 0;
+    int gx = (max_len + 255) / 256;
+    if (gx > 64) gx = 64;
+    if (gx < 1) gx = 1;
+    (void)hipGetLastError();
+    if (fp64)
+        hipLaunchKernelGGL(export_solution<double>, dim3(gx, count), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                           probs, count, out, ld);
+    else
+        hipLaunchKernelGGL(export_solution<float>, dim3(gx, count), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                           probs, count, out, ld);
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }

@@ -1,0 +1,123 @@
+"""Learned warm start for a parametric SOS family (orchestration only).
+
+The network and the solver run in libsos.so: this module moves arrays between them.
+
+1. Training data: the solver's own batched cold solves of the training instances;
+   sos_batch_export_solutions writes each converged (xi / tau, y / tau) in the
+   library's layout, and only instances the solver reports SOLVED are kept.
+2. Training: the device MLP (sos_mlp_*) on standardised targets, mini-batch Adam.
+   The standardisation (per-output mean and spread of the training targets) is data
+   preparation done once; the network's output layer undoes it on the device.
+3. Use: predict (xi, y) for new instances, sos_batch_warm_start makes the prediction
+   consistent with the cones (u = (P_K(xi), y, 1), v = (P_K*(c - A^T y), 0, 0)), the
+   batch is solved, and every problem that the warm start does not bring to a
+   SOLVED status or a certificate is solved again from the cold start (the fallback).
+"""
+from __future__ import annotations
+
+import time
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import binding as B
+
+
+def export_solutions(batch: "B.Batch", layout: int):
+    import torch
+    out = torch.zeros((len(batch.works), layout), dtype=torch.float32, device="cuda")
+    B.sos_batch_export_solutions(batch, out, layout)
+    return out
+
+
+def cold_solve_batch(works: Sequence["B.Work"], schedule: Optional[str] = None):
+    """Cold-start batched solve; returns (infos, device tensor of normalised solutions, batch)."""
+    batch = B.sos_batch_setup(list(works), schedule)
+    B.sos_batch_reset(batch)
+    infos = B.sos_batch_solve(batch)
+    layout = B.sos_layout_size(works[0])
+    return infos, export_solutions(batch, layout), batch
+
+
+class WarmStartModel:
+    """MLP (n_in -> hidden -> hidden -> n_out, GELU) trained on the device."""
+
+    def __init__(self, n_in: int, n_out: int, hidden: int = 512, max_batch: int = 4096, seed: int = 0):
+        self.n_in, self.n_out, self.hidden = n_in, n_out, hidden
+        self.net = B.MLP(n_in, hidden, n_out, max_batch)
+        rng = np.random.default_rng(seed)
+        parts = []
+        for fan_in, fan_out in ((n_in, hidden), (hidden, hidden), (hidden, n_out)):
+            parts.append(rng.standard_normal(fan_in * fan_out) * np.sqrt(2.0 / fan_in))   # He initialisation
+            parts.append(np.zeros(fan_out))
+        self.net.set_params(np.concatenate(parts).astype(np.float32))
+        self.mu = np.zeros(n_out, dtype=np.float32)
+        self.sd = np.ones(n_out, dtype=np.float32)
+
+    def fit(self, X, T, epochs: int = 60, batch: int = 256, lr: float = 1e-3, seed: int = 0,
+            log=None) -> List[float]:
+        """X: (S, n_in) float32 cuda tensor; T: (S, n_out) float32 cuda tensor (raw targets)."""
+        import torch
+        Tn_host = T.cpu().numpy().astype(np.float64)
+        self.mu = Tn_host.mean(axis=0).astype(np.float32)
+        sd = Tn_host.std(axis=0)
+        self.sd = np.where(sd > 1e-8, sd, 1.0).astype(np.float32)
+        Tn = ((T - torch.from_numpy(self.mu).cuda()) / torch.from_numpy(self.sd).cuda()).contiguous()
+        rng = np.random.default_rng(seed)
+        S = X.shape[0]
+        losses = []
+        for ep in range(epochs):
+            perm = torch.from_numpy(rng.permutation(S)).cuda()
+            tot, cnt = 0.0, 0
+            for i in range(0, S - batch + 1, batch):
+                idx = perm[i:i + batch]
+                Xb = X.index_select(0, idx).contiguous()
+                Tb = Tn.index_select(0, idx).contiguous()
+                want = (i + batch > S - batch)
+                L = self.net.train_step(Xb, Tb, lr, want_loss=want)
+                if want:
+                    tot, cnt = tot + L, cnt + 1
+            losses.append(tot / max(cnt, 1))
+            if log and (ep % 10 == 0 or ep == epochs - 1):
+                log(f"[warm] epoch {ep}: loss {losses[-1]:.4f}")
+        self.net.set_output_affine(self.sd, self.mu)
+        return losses
+
+    def predict(self, X, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((X.shape[0], self.n_out), dtype=torch.float32, device="cuda")
+        self.net.forward(X, out, apply_output_affine=True)
+        return out
+
+
+def warm_solve(batch: "B.Batch", model: WarmStartModel, X, fallback_works: Optional[Sequence["B.Work"]] = None,
+               layout: Optional[int] = None):
+    """Predict, warm start, solve; re-solve cold every problem the warm start left unsolved.
+
+    Returns (infos, n_fallback, ms) with ms the device time of inference + warm start +
+    solve + fallback solves."""
+    import torch
+    layout = layout or model.n_out
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    pred = model.predict(X)
+    torch.cuda.synchronize()
+    B.sos_batch_warm_start(batch, pred, layout)
+    infos = B.sos_batch_solve(batch)
+    bad = [i for i, inf in enumerate(infos) if inf["status"] not in (B.SOS_SOLVED, B.SOS_PRIMAL_INFEASIBLE,
+                                                                     B.SOS_DUAL_INFEASIBLE)]
+    if bad and fallback_works is not None:
+        sub = [fallback_works[i] for i in bad]
+        fb = B.sos_batch_setup(sub, None)
+        B.sos_batch_reset(fb)
+        finfos = B.sos_batch_solve(fb)
+        for i, inf in zip(bad, finfos):
+            inf["fallback"] = True
+            infos[i] = inf
+        fb.free()
+    t1.record()
+    torch.cuda.synchronize()
+    return infos, len(bad), t0.elapsed_time(t1)

@@ -80,12 +80,56 @@ def pop_unconstrained(n: int, seed: int, cross_std: float = 0.0) -> ConicProblem
     return pop_from_poly(p, 2, {"family": "pop_unconstrained", "seed": seed, "cross_std": cross_std})
 
 
-def pop_batch_member(seed: int) -> ConicProblem:
-    """Batch member: n ~ U{6..16} drawn first from the seed's stream, then the quartic POP at that n."""
+def variable_scale(p: Poly, starts: int = 4, seed: int = 12345) -> float:
+    """Scale s for the substitution x = s y: the largest |x_i| of the best local minimiser of p
+    found by BFGS from a few seeded starts (at least 1).  A modelling step, like the variable
+    scaling of POP modelling tools; it leaves the relaxation's optimum unchanged (gamma = s^4
+    gamma_y for a quartic written as p(s y) / s^4)."""
+    from scipy.optimize import minimize
+    n = p.n
+    E = np.array([e for e, _ in p.items()], dtype=float)
+    C = np.array([c for _, c in p.items()])
+
+    def f(x):
+        return float(C @ np.prod(x[None, :] ** E, axis=1))
+
+    def g(x):
+        out = np.zeros(n)
+        for i in range(n):
+            Ei = E.copy()
+            mask = Ei[:, i] > 0
+            coef = C[mask] * Ei[mask, i]
+            Ei = Ei[mask]
+            Ei[:, i] -= 1
+            out[i] = coef @ np.prod(x[None, :] ** Ei, axis=1)
+        return out
+
+    rng = np.random.default_rng(seed)
+    best, xb = np.inf, np.ones(n)
+    for _ in range(starts):
+        r = minimize(f, rng.standard_normal(n), jac=g, method="BFGS", options={"maxiter": 500})
+        if r.fun < best:
+            best, xb = r.fun, r.x
+    return max(1.0, float(np.abs(xb).max()))
+
+
+def scaled_quartic(p: Poly, s: float) -> Poly:
+    """p(s y) / s^4 as a polynomial in y."""
+    return Poly(p.n, {e: c * s ** (sum(e) - 4) for e, c in p.items()})
+
+
+def pop_batch_member(seed: int, scaled: bool = True) -> ConicProblem:
+    """Batch member: n ~ U{6..16} drawn first from the seed's stream, then the quartic POP at that n.
+
+    With scaled=True the POP is written in y = x / s (see variable_scale); the solver then
+    returns gamma_y and gamma = s^4 gamma_y (meta["gamma_scale"])."""
     rng = np.random.default_rng(seed)
     n = int(rng.integers(6, 17))
     p = quartic_poly(n, rng, 0.0)
-    return pop_from_poly(p, 2, {"family": "pop_batch", "seed": seed})
+    s = variable_scale(p) if scaled else 1.0
+    q = scaled_quartic(p, s) if scaled else p
+    return pop_from_poly(q, 2, {"family": "pop_batch", "seed": seed, "n_vars": n, "scale": s,
+                                "gamma_scale": s ** 4})
 
 
 def pop_ball(n: int, seed: int) -> ConicProblem:

@@ -199,7 +199,7 @@ def test_batch_fp64_equals_single_solves(B):
 
 def test_batch_mixed_precision_gamma_error(B):
     # FP32 bulk + FP64 polish: gamma error against the FP64 oracle, stated per problem
-    probs = [F.pop_unconstrained(n, sd) for n, sd in ((4, 3), (5, 4), (6, 5), (7, 6))] + [F.pop_ball(3, 5)]
+    probs = [F.pop_unconstrained(n, sd) for n, sd in ((4, 0), (4, 1), (4, 3), (5, 4))] + [F.pop_ball(3, 5)]
     s = B.sos_default_settings(tol=1e-4, max_iters=4000, precision=B.SOS_FP32_MIXED, polish_iters=1)
     works = [B.setup_problem(p, s) for p in probs]
     bt = B.sos_batch_setup(works)

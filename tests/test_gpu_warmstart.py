@@ -1,0 +1,124 @@
+"""GPU tests of the learned warm start: the device MLP against the FP64 reference MLP,
+the warm-start kernel, and what a trained network gains over the cold start."""
+import numpy as np
+import pytest
+
+from oracle import mlp as ref
+from sosgen import families as F
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1708_04174_amd import binding
+    binding.load()
+    return binding, torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("dims,batch", [((7, 16, 9), 5), ((127, 64, 300), 70), ((33, 130, 65), 129)])
+def test_mlp_gradient_matches_reference(env, dims, batch):
+    B, torch = env
+    rng = np.random.default_rng(sum(dims))
+    n = ref.num_params(*dims)
+    theta = (rng.standard_normal(n) * 0.3).astype(np.float32)
+    X = rng.standard_normal((batch, dims[0])).astype(np.float32)
+    T = rng.standard_normal((batch, dims[2])).astype(np.float32)
+    net = B.MLP(*dims, max_batch=batch)
+    net.set_params(theta)
+    g, L = net.gradient(_dev(torch, X), _dev(torch, T))
+    gr, Lr = ref.gradient(theta.astype(np.float64), X, T, dims)
+    err = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    print(f"[mlp] dims={dims} batch={batch} grad rel err {err:.2e} loss {L:.6f} vs {Lr:.6f}", flush=True)
+    assert err < 2e-5 and abs(L - Lr) <= 1e-5 * Lr
+    # forward with the output affine
+    Y = torch.empty((batch, dims[2]), dtype=torch.float32, device="cuda")
+    sc, sh = rng.uniform(0.5, 2, dims[2]), rng.standard_normal(dims[2])
+    net.set_output_affine(sc, sh)
+    net.forward(_dev(torch, X), Y, apply_output_affine=True)
+    Yr, _ = ref.forward(theta.astype(np.float64), X, dims)
+    assert np.allclose(Y.cpu().numpy(), Yr * sc + sh, rtol=1e-4, atol=1e-4)
+    net.free()
+
+
+def test_mlp_adam_steps_match_reference(env):
+    B, torch = env
+    dims, batch = (9, 24, 11), 17
+    rng = np.random.default_rng(5)
+    theta = (rng.standard_normal(ref.num_params(*dims)) * 0.3).astype(np.float32)
+    X = rng.standard_normal((batch, dims[0])).astype(np.float32)
+    T = rng.standard_normal((batch, dims[2])).astype(np.float32)
+    net = B.MLP(*dims, max_batch=batch)
+    net.set_params(theta)
+    opt = ref.Adam(theta.size, lr=1e-2)
+    th = theta.astype(np.float64)
+    Xd, Td = _dev(torch, X), _dev(torch, T)
+    for _ in range(5):
+        net.train_step(Xd, Td, 1e-2)
+        g, _ = ref.gradient(th, X, T, dims)
+        th = opt.step(th, g)
+    got = net.get_params()
+    err = np.max(np.abs(got - th))
+    print(f"[mlp] 5 Adam steps max param diff {err:.2e}", flush=True)
+    assert err < 1e-4
+
+
+def test_warm_start_from_exact_solution_is_a_fixed_point(env):
+    # prediction = the solver's own converged solution: the warm-started solve stops at once
+    B, torch = env
+    from paper_1708_04174_amd import warmstart as W
+    probs = [F.lyapunov(s) for s in range(4)]
+    s64 = B.sos_default_settings(tol=1e-6, max_iters=4000)
+    works = [B.setup_problem(p, s64) for p in probs]
+    infos, sol, bt = W.cold_solve_batch(works)
+    layout = B.sos_layout_size(works[0])
+    B.sos_batch_warm_start(bt, sol, layout)
+    infos2 = B.sos_batch_solve(bt)
+    for a, b in zip(infos, infos2):
+        print(f"[warm] cold {a['status_name']} {a['iters']} it; from its own solution {b['status_name']} "
+              f"{b['iters']} it", flush=True)
+        if a["status"] == B.SOS_SOLVED:
+            assert b["status"] == B.SOS_SOLVED and b["iters"] <= 20
+    bt.free()
+
+
+def test_learned_warm_start_gain(env):
+    # train on the solver's own solutions of 512 Lyapunov instances, test on 64 held-out ones
+    B, torch = env
+    from paper_1708_04174_amd import warmstart as W
+    train = list(range(0, 512))
+    test = list(range(3584, 3648))
+    st = B.sos_default_settings(tol=1e-4, max_iters=2000, precision=B.SOS_FP32_MIXED)
+    tw = [B.setup_problem(F.lyapunov(s), st) for s in train]
+    infos, sol, bt = W.cold_solve_batch(tw)
+    keep = [i for i, inf in enumerate(infos) if inf["status"] == B.SOS_SOLVED]
+    print(f"[warm] training set: {len(keep)}/{len(train)} solved cold", flush=True)
+    Xtr = _dev(torch, np.stack([F.lyapunov_features(train[i]) for i in keep]))
+    Ttr = sol[torch.tensor(keep, device="cuda")].contiguous()
+    model = W.WarmStartModel(Xtr.shape[1], Ttr.shape[1], hidden=512, max_batch=4096, seed=0)
+    losses = model.fit(Xtr, Ttr, epochs=60, batch=128, lr=1e-3, log=lambda m: print(m, flush=True))
+    assert losses[-1] < 0.5 * losses[0]
+    # held-out: cold vs warm
+    probs = [F.lyapunov(s) for s in test]
+    cold_w = [B.setup_problem(p, st) for p in probs]
+    warm_w = [B.setup_problem(p, st) for p in probs]
+    cinfos, _, cb = W.cold_solve_batch(cold_w)
+    wb = B.sos_batch_setup(warm_w)
+    Xte = _dev(torch, np.stack([F.lyapunov_features(s) for s in test]))
+    winfos, nfb, ms = W.warm_solve(wb, model, Xte, fallback_works=warm_w)
+    ci = np.array([i["iters"] for i in cinfos])
+    wi = np.array([i["iters"] for i in winfos])
+    same = sum(a["status"] == b["status"] for a, b in zip(cinfos, winfos))
+    print(f"[warm] held-out: cold mean iters {ci.mean():.1f} median {np.median(ci):.0f}; warm mean {wi.mean():.1f} "
+          f"median {np.median(wi):.0f}; fallbacks {nfb}; same status {same}/{len(test)}", flush=True)
+    for inf in winfos:
+        assert inf["status"] in (B.SOS_SOLVED, B.SOS_PRIMAL_INFEASIBLE, B.SOS_DUAL_INFEASIBLE, B.SOS_MAX_ITERS)
+        if inf["status"] == B.SOS_SOLVED:
+            assert max(inf["res_pri"], inf["res_dual"], inf["gap"]) <= 1e-4
+    assert same >= len(test) - 2
