@@ -1,12 +1,18 @@
 #!/usr/bin/env python3
 """SOS solves/sec at 1e-4 residual on one MI355X.
 
-A step is one batched solve of the whole workload from the cold start (or from the
-learned warm start where the workload has one): every problem of the batch is run
-to max(r_p, r_d, r_g) <= 1e-4 (FP64-measured) or to an infeasibility certificate.
-Inputs are set up and resident in HBM before the timed region.
+A step is one pass of the whole path over one batch of synthetic SOS programs with
+inputs already resident on the GPU: the learned warm start (MLP inference on the
+device, the warm-start kernel), the batched persistent solve (FP32 bulk, FP64 Schur
+solve / theta / tau-kappa / residuals, FP64 polish), and cold re-solves of whatever the
+warm start left unsolved.  A solve counts when its FP64 max(r_p, r_d, r_g) <= 1e-4 or
+it ends in an infeasibility certificate.
 
-Prints ONE JSON line (see the README of the repository for the fields).
+Default workload: 512 held-out Lyapunov programs (n = 6, quartic V; Gram blocks 28 and
+84, m = 1134).  The warm-start model is trained beforehand (untimed) on the solver's
+own cold solutions of the 3584 training programs of the same family.
+
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -24,31 +30,11 @@ sys.path.insert(0, ROOT)
 METRIC = "SOS solves/sec at 1e-4 residual: batched FP32+warm-start vs plain FP64 ADMM"
 PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector peak
 PEAK_FP64_TFLOPS = 78.6
+OK_STATUS = (1, 2, 3)
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-# ----------------------------------------------------------------------------- workloads
-def workload_pop_batch(count: int):
-    from sosgen import families as F
-    return [F.pop_batch_member(s) for s in range(count)]
-
-
-def workload_lyapunov_test(count: int):
-    from sosgen import families as F
-    return [F.lyapunov(s) for s in range(3584, 3584 + count)]
-
-
-WORKLOADS = {
-    "pop_batch_512": dict(make=lambda: workload_pop_batch(512), count=512, plain_sample=4,
-                          desc="512 unconstrained quartic POPs, n ~ U{6..16} (Gram 28..153, m 210..4845), "
-                               "seeds 0..511, variables scaled, batched FP32 bulk + FP64 polish, cold start"),
-    "lyapunov_512": dict(make=lambda: workload_lyapunov_test(512), count=512, plain_sample=32,
-                         desc="512 Lyapunov programs, n = 6, quartic V (t = 203 free, Gram 28 and 84, m = 1134), "
-                              "seeds 3584..4095, batched FP32 bulk + FP64 polish, cold start"),
-}
 
 
 def eig_flops(N: int) -> float:
@@ -60,13 +46,12 @@ def eig_flops(N: int) -> float:
 
 def iter_flops(prob) -> float:
     """Algorithmic flops of one ADMM iteration: the PSD projections plus the affine step
-    (two sparse products with A: 4 nnz, the Woodbury correction 4 nnz(A_f) + 2 k^2, and
-    about 12 vector flops per entry of u)."""
-    nnz = prob.A.nnz
-    return sum(eig_flops(N) for N in prob.psd_dims) + 4.0 * nnz + 12.0 * (prob.n + prob.m)
+    (two sparse products with A: 4 nnz; Woodbury correction about 4 nnz(A_f) + 2 k^2;
+    about 12 flops per entry of u)."""
+    k = prob.n_free
+    return sum(eig_flops(N) for N in prob.psd_dims) + 4.0 * prob.A.nnz + 2.0 * k * k + 12.0 * (prob.n + prob.m)
 
 
-# ----------------------------------------------------------------------------- CPU baseline
 def cpu_baseline(probs, budget_s: float, tol: float):
     from threadpoolctl import threadpool_limits
 
@@ -77,108 +62,163 @@ def cpu_baseline(probs, budget_s: float, tol: float):
         for p in probs:
             r = Oracle.from_problem(p).solve(tol=tol, max_iters=2000, check_every=10)
             done += 1
-            solved += r.status in (1, 2, 3)
-            names.append(f"seed{p.meta.get('seed')}(N={max(p.psd_dims)})")
+            solved += r.status in OK_STATUS
+            names.append(f"seed{p.meta.get('seed')}")
             if time.perf_counter() - t0 > budget_s:
                 break
     el = time.perf_counter() - t0
     return {"value": solved / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} problems of the workload solved one at a time in FP64 with I + A A^T "
-                      f"factored directly, 1 BLAS thread: {', '.join(names)}; {el:.1f} s"}
+            "sample": f"{done} problems of the workload, one at a time, FP64, I + A A^T factored directly, "
+                      f"1 BLAS thread ({', '.join(names[:6])}{', ...' if len(names) > 6 else ''}); {el:.1f} s"}
 
 
-# ----------------------------------------------------------------------------- main
+def load_schedule(name: str, override):
+    """The launch schedule as a JSON string: --schedule names a file or is inline JSON."""
+    if override:
+        text = open(override).read() if os.path.exists(override) else override
+        try:
+            json.loads(text)
+        except json.JSONDecodeError:
+            sys.exit(f"--schedule: {override!r} is neither a JSON file nor inline JSON")
+        return text
+    f = os.path.join(ROOT, "paper_1708_04174_amd", "schedules", f"{name}.json")
+    return open(f).read() if os.path.exists(f) else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="lyapunov_512", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="lyapunov_512", choices=["lyapunov_512", "pop_batch_512"])
     ap.add_argument("--tol", type=float, default=1e-4)
-    ap.add_argument("--schedule", default=None, help="schedule JSON string or file")
-    ap.add_argument("--plain-sample", type=int, default=0, help="0 = the workload's default")
+    ap.add_argument("--schedule", default=None)
+    ap.add_argument("--train-count", type=int, default=3584)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--plain-sample", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this solver runs on one GPU; a batch would be split across GPUs by "
-                                   "problem (see the design notes), which is not part of this build",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU: a batch would be split across GPUs by problem "
+                                   "(see the design notes), which is not part of it", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     from paper_1708_04174_amd import binding as B
+    from paper_1708_04174_amd import warmstart as W
+    from paper_1708_04174_amd import workloads as WL
 
-    wl = WORKLOADS[args.workload]
+    lyap = args.workload == "lyapunov_512"
     t0 = time.perf_counter()
-    probs = wl["make"]()
-    log(f"[bench] generated {len(probs)} problems in {time.perf_counter() - t0:.1f}s")
-    sched = args.schedule
-    if sched and os.path.exists(sched):
-        sched = open(sched).read()
-    if sched is None:
-        default_sched = os.path.join(ROOT, "paper_1708_04174_amd", "schedules", f"{args.workload}.json")
-        if os.path.exists(default_sched):
-            sched = open(default_sched).read()
-
+    if lyap:
+        test_seeds = list(WL.LYAP_TEST)
+        probs = WL.generate("lyapunov", test_seeds)
+        train_seeds = list(WL.LYAP_TRAIN)[:args.train_count]
+        train_probs = WL.generate("lyapunov", train_seeds) if train_seeds else []
+    else:
+        probs = WL.generate("pop_batch", range(512))
+        train_probs = []
+    log(f"[bench] generated {len(probs)} + {len(train_probs)} problems in {time.perf_counter() - t0:.1f}s")
+    sched = load_schedule(args.workload, args.schedule)
     st = B.sos_default_settings(tol=args.tol, max_iters=2000, check_every=10,
                                 precision=B.SOS_FP32_MIXED, polish_iters=1)
     t0 = time.perf_counter()
     works = [B.setup_problem(p, st) for p in probs]
     batch = B.sos_batch_setup(works, sched)
+    layout = B.sos_layout_size(works[0])
     log(f"[bench] setup {time.perf_counter() - t0:.1f}s")
 
-    def one_step():
+    # ---------------------------------------------------------------- warm-start model (untimed)
+    model, train_info = None, None
+    if lyap and train_probs:
+        t0 = time.perf_counter()
+        X, T = [], []
+        for i in range(0, len(train_probs), 512):
+            chunk = train_probs[i:i + 512]
+            tw = [B.setup_problem(p, st) for p in chunk]
+            infos, sol, tb = W.cold_solve_batch(tw, sched)
+            keep = [j for j, inf in enumerate(infos) if inf["status"] == B.SOS_SOLVED]
+            X.append(WL.lyapunov_features([train_seeds[i + j] for j in keep]))
+            T.append(sol[torch.tensor(keep, device="cuda")].contiguous())
+            tb.free()
+            for w in tw:
+                w.free()
+            log(f"[bench] training data {i + len(chunk)}/{len(train_probs)}: {len(keep)} solved")
+        Xtr = torch.from_numpy(np.concatenate(X)).cuda()
+        Ttr = torch.cat(T).contiguous()
+        t1 = time.perf_counter()
+        model = W.WarmStartModel(Xtr.shape[1], Ttr.shape[1], hidden=512, max_batch=4096, seed=0)
+        losses = model.fit(Xtr, Ttr, epochs=args.epochs, batch=256, lr=1e-3, log=log)
+        train_info = {"instances": int(Xtr.shape[0]), "epochs": args.epochs, "final_loss": losses[-1],
+                      "data_s": t1 - t0, "fit_s": time.perf_counter() - t1}
+        log(f"[bench] model: {train_info}")
+        Xte = torch.from_numpy(WL.lyapunov_features(test_seeds)).cuda()
+
+    # ---------------------------------------------------------------- cold batched (ablation)
+    def cold_step():
         B.sos_batch_reset(batch)
         torch.cuda.synchronize()
+        t = time.perf_counter()
         infos = B.sos_batch_solve(batch)
-        return infos, B.sos_batch_last_ms(batch), B.sos_batch_phase_ms(batch, 0), B.sos_batch_phase_ms(batch, 1)
+        torch.cuda.synchronize()
+        return infos, (time.perf_counter() - t) * 1e3
 
+    cinfos, cms = cold_step()
+    cold = {"value": sum(i["status"] in OK_STATUS for i in cinfos) / (cms / 1e3), "ms": cms,
+            "iters_mean": float(np.mean([i["iters"] for i in cinfos]))}
+    log(f"[bench] cold batched: {cold}")
+
+    def warm_step():
+        B.sos_batch_reset(batch)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        infos, nfb, _ = W.warm_solve(batch, model, Xte, fallback_works=works, layout=layout)
+        torch.cuda.synchronize()
+        return infos, (time.perf_counter() - t) * 1e3, nfb
+
+    step = (lambda: warm_step()) if model is not None else (lambda: cold_step() + (0,))
     for i in range(args.warmup):
-        infos, ms, p0, p1 = one_step()
-        log(f"[bench] warmup {i}: {ms:.1f} ms (solve kernel {p0:.1f} ms, polish {p1:.1f} ms)")
-
-    step_ms, k0_ms, k1_ms, counted = [], [], [], []
-    fp32_iters = None
+        _, ms, _ = step()
+        log(f"[bench] warmup {i}: {ms:.1f} ms")
+    step_ms, counted, kms, pms, fbs = [], [], [], [], []
+    infos = None
     for i in range(args.steps):
         torch.cuda.synchronize()
-        infos, ms, p0, p1 = one_step()
-        torch.cuda.synchronize()
-        ok = [inf["status"] in (1, 2, 3) for inf in infos]
+        infos, ms, nfb = step()
+        ok = sum(inf["status"] in OK_STATUS for inf in infos)
         step_ms.append(ms)
-        k0_ms.append(p0)
-        k1_ms.append(p1)
-        counted.append(sum(ok))
-        fp32_iters = [inf["iters"] - inf["polish_iters"] for inf in infos]
-        log(f"[bench] step {i}: {ms:.1f} ms, {sum(ok)}/{len(ok)} solved "
-            f"(solve kernel {p0:.1f} ms, polish {p1:.1f} ms)")
-
+        counted.append(ok)
+        kms.append(B.sos_batch_phase_ms(batch, 0))
+        pms.append(B.sos_batch_phase_ms(batch, 1))
+        fbs.append(nfb)
+        log(f"[bench] step {i}: {ms:.1f} ms, {ok}/{len(infos)} counted, fallbacks {nfb}, "
+            f"solve kernel {kms[-1]:.1f} ms, polish kernel {pms[-1]:.1f} ms")
     total_ms = float(np.sum(step_ms))
     value = float(np.sum(counted)) / (total_ms / 1e3)
     statuses = {}
     for inf in infos:
         statuses[inf["status_name"]] = statuses.get(inf["status_name"], 0) + 1
     iters = np.array([inf["iters"] for inf in infos])
-    worst = max(max(inf["res_pri"], inf["res_dual"], inf["gap"]) for inf in infos if inf["status"] == 1) \
-        if any(inf["status"] == 1 for inf in infos) else None
+    solved = [inf for inf in infos if inf["status"] == 1]
+    worst = max(max(i["res_pri"], i["res_dual"], i["gap"]) for i in solved) if solved else None
 
-    # roofline of the dominant kernel: the persistent FP32 solve kernel
-    flops = sum(it * iter_flops(p) for it, p in zip(fp32_iters, probs))
-    k_ms = float(np.mean(k0_ms))
-    achieved = flops / (k_ms / 1e3) / 1e12
+    # roofline of the dominant kernel (the persistent FP32 solve kernel of the last step)
+    fp32_iters = [inf["iters"] - inf["polish_iters"] for inf in infos]
+    flops = float(sum(it * iter_flops(p) for it, p in zip(fp32_iters, probs)))
+    k_ms = float(kms[-1])
+    achieved = flops / (k_ms / 1e3) / 1e12 if k_ms > 0 else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                "kernel": "admm_persistent<float>", "kernel_ms": k_ms,
-                "algorithmic_flops_per_launch": flops}
+                "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": None,
+                "kernel": "admm_persistent<float>", "kernel_ms": k_ms, "algorithmic_flops_per_launch": flops}
 
-    # plain FP64 arm: one problem at a time, every step in FP64, cold start
     plain = None
     if not args.no_plain:
-        ns = args.plain_sample or wl["plain_sample"]
+        ns = args.plain_sample or (32 if lyap else 4)
         idx = np.linspace(0, len(probs) - 1, ns).astype(int)
         s64 = B.sos_default_settings(tol=args.tol, max_iters=2000, check_every=10, precision=B.SOS_FP64)
         tms, ok64 = 0.0, 0
@@ -186,30 +226,36 @@ def main():
             w = B.setup_problem(probs[i], s64)
             inf = B.sos_solve(w)
             tms += inf["solve_ms"]
-            ok64 += inf["status"] in (1, 2, 3)
+            ok64 += inf["status"] in OK_STATUS
             w.free()
-        plain = {"value": ok64 / (tms / 1e3), "unit": "solves/s", "sample": f"{len(idx)} problems spread over the "
-                 "workload, sos_solve one at a time in FP64", "ms_total": tms}
+        plain = {"value": ok64 / (tms / 1e3), "unit": "solves/s", "ms_total": tms,
+                 "sample": f"{len(idx)} problems spread over the workload, sos_solve one at a time, every step FP64, "
+                           "cold start"}
         log(f"[bench] plain FP64: {plain['value']:.2f} solves/s")
 
     cpu = None
     if not args.no_cpu_baseline:
-        order = sorted(range(len(probs)), key=lambda i: max(probs[i].psd_dims))
-        sample = [probs[i] for i in order[::max(1, len(order) // 12)]]
+        sample = [probs[i] for i in range(0, len(probs), max(1, len(probs) // 16))]
         cpu = cpu_baseline(sample, args.cpu_budget, args.tol)
         log(f"[bench] cpu baseline: {cpu['value']:.3f} solves/s")
 
+    desc = ("512 held-out Lyapunov programs (n = 6, quartic V: 203 free variables, Gram blocks 28 and 84, "
+            "m = 1134; seeds 3584..4095), learned warm start + batched FP32 bulk / FP64 polish"
+            if lyap else "512 quartic POPs (n ~ U{6..16}, Gram 28..153, m 210..4845, scaled variables; seeds 0..511), "
+            "batched FP32 bulk / FP64 polish, cold start")
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": total_ms / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": args.workload, "description": wl["desc"], "problems": len(probs),
-                   "tol": args.tol, "statuses": statuses, "iters_median": float(np.median(iters)),
-                   "iters_max": int(iters.max()), "worst_solved_residual": worst,
-                   "phase_ms": {"solve_kernel": k_ms, "polish_kernel": float(np.mean(k1_ms))}},
+        "config": {"workload": args.workload, "description": desc, "problems": len(probs), "tol": args.tol,
+                   "statuses": statuses, "iters_mean": float(iters.mean()), "iters_median": float(np.median(iters)),
+                   "iters_max": int(iters.max()), "fallbacks": int(np.sum(fbs)), "worst_solved_residual": worst,
+                   "phase_ms": {"solve_kernel": k_ms, "polish_kernel": float(pms[-1])},
+                   "schedule": json.loads(sched) if sched else None, "warm_start_model": train_info},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain_fp64": plain,
+        "batched_cold_fp32": cold,
         "speedup_vs_plain_fp64": (value / plain["value"]) if plain else None,
     }
     print(json.dumps(out), flush=True)

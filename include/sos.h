@@ -104,6 +104,7 @@ typedef struct {
     double  tau, kappa;
     double  setup_ms, solve_ms;
     double  eig_sweeps;      /* mean eigensolver sweeps per block projection in the last launch */
+    double  affine_ms, eig_ms, resid_ms;   /* device time of the last launch by phase (one workgroup's clock) */
 } sos_info;
 
 /* Fills *s with tol 1e-4, max_iters 2000, check_every 10, alpha 1, SOS_FP64,

@@ -1,0 +1,112 @@
+"""Autotuner for the batched solver's launch schedule.
+
+Times fixed-length batched runs (the same persistent kernel the solve uses, stopped after
+a fixed number of iterations) and picks
+  1. per block-size bucket (N < 32, 64, 96, 128, 192, 256, larger): the lanes that
+     share one Jacobi column pair (8, 16 or 32) - the tile of the eigensolver;
+  2. for the whole batch: threads per workgroup and resident workgroups per CU (which
+     also sets the LDS each workgroup may use).
+Writes the schedule JSON that sos_batch_setup reads.
+
+    python -m paper_1708_04174_amd.autotune --workload lyapunov --out schedules/lyapunov_512.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+from collections import defaultdict
+
+import numpy as np
+
+from . import binding as B
+from . import workloads as WL
+
+BUCKETS = [32, 64, 96, 128, 192, 256, 1 << 30]
+KEYS = ["gs_n32", "gs_n64", "gs_n96", "gs_n128", "gs_n192", "gs_n256", "gs_big"]
+
+
+def bucket_of(N: int) -> int:
+    for i, b in enumerate(BUCKETS):
+        if N < b:
+            return i
+    return len(BUCKETS) - 1
+
+
+def time_schedule(works, sched: dict, reps: int = 2) -> float:
+    bt = B.sos_batch_setup(works, json.dumps(sched))
+    best = np.inf
+    for _ in range(reps):
+        B.sos_batch_reset(bt)
+        B.sos_batch_solve(bt)
+        best = min(best, B.sos_batch_phase_ms(bt, 0))
+    bt.free()
+    return best
+
+
+def tune(probs, precision: int, iters: int = 40, sample: int = 64, log=print) -> dict:
+    # fixed-length runs: an unreachable tolerance makes every problem run `iters` iterations
+    st = B.sos_default_settings(tol=1e-14, max_iters=iters, precision=precision, polish_iters=1)
+    base = {"block_threads": 256, "wg_per_cu": 2, "max_sweeps": 60, "warm_eig": 1, "use_graph": 0}
+    byb = defaultdict(list)
+    for i, p in enumerate(probs):
+        for b in sorted({bucket_of(N) for N in p.psd_dims if N > 1}):
+            byb[b].append(i)
+    sched = dict(base)
+    for k in KEYS:
+        sched[k] = 16
+    for b, idx in sorted(byb.items()):
+        sub = [probs[i] for i in idx[:sample]]
+        works = [B.setup_problem(p, st) for p in sub]
+        res = {}
+        for gs in (8, 16, 32):
+            s = dict(sched)
+            s[KEYS[b]] = gs
+            res[gs] = time_schedule(works, s)
+        sched[KEYS[b]] = min(res, key=res.get)
+        log(f"[tune] bucket N<{BUCKETS[b]}: {len(sub)} problems, ms by lanes/pair {res} -> {sched[KEYS[b]]}")
+        for w in works:
+            w.free()
+    rng = np.random.default_rng(0)
+    pick = rng.choice(len(probs), size=min(len(probs), 4 * sample), replace=False)
+    works = [B.setup_problem(probs[i], st) for i in pick]
+    res = {}
+    for thr in (128, 256, 512):
+        for wpc in (1, 2, 4):
+            if thr * wpc > 1024:
+                continue
+            s = dict(sched)
+            s["block_threads"], s["wg_per_cu"] = thr, wpc
+            res[(thr, wpc)] = time_schedule(works, s)
+            log(f"[tune] threads {thr} wg/CU {wpc}: {res[(thr, wpc)]:.2f} ms")
+    thr, wpc = min(res, key=res.get)
+    sched["block_threads"], sched["wg_per_cu"] = thr, wpc
+    sched["use_graph"] = 1
+    for w in works:
+        w.free()
+    sched["tuned"] = {"iters": iters, "precision": "fp32_mixed" if precision == B.SOS_FP32_MIXED else "fp64",
+                      "problems": len(probs), "when": time.strftime("%Y-%m-%d")}
+    return sched
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", choices=["lyapunov", "pop_batch"], default="lyapunov")
+    ap.add_argument("--count", type=int, default=512)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args()
+    import torch
+    assert torch.cuda.is_available()
+    seeds = WL.LYAP_TEST if a.workload == "lyapunov" else range(a.count)
+    probs = WL.generate(a.workload, list(seeds)[:a.count])
+    prec = B.SOS_FP32_MIXED if a.precision == "fp32" else B.SOS_FP64
+    sched = tune(probs, prec, log=lambda m: print(m, file=sys.stderr, flush=True))
+    with open(a.out, "w") as f:
+        json.dump(sched, f, indent=1)
+    print(json.dumps(sched))
+
+
+if __name__ == "__main__":
+    main()

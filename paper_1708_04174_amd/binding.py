@@ -57,7 +57,8 @@ class sos_info(C.Structure):
                 ("polish_iters", C.c_int32), ("pobj", C.c_double), ("dobj", C.c_double),
                 ("res_pri", C.c_double), ("res_dual", C.c_double), ("gap", C.c_double),
                 ("tau", C.c_double), ("kappa", C.c_double), ("setup_ms", C.c_double),
-                ("solve_ms", C.c_double), ("eig_sweeps", C.c_double)]
+                ("solve_ms", C.c_double), ("eig_sweeps", C.c_double), ("affine_ms", C.c_double),
+                ("eig_ms", C.c_double), ("resid_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -312,12 +313,19 @@ def sos_layout_size(w: Work) -> int:
     return int(load().sos_layout_size(w.handle))
 
 
+def _check_rows(t, count: int, ld: int):
+    if t.dim() != 2 or t.shape[0] < count or t.shape[1] != ld or t.stride(0) != ld:
+        raise ValueError(f"expected a contiguous ({count}, {ld}) float32 cuda tensor, got {tuple(t.shape)}")
+
+
 def sos_batch_warm_start(batch: Batch, pred, ld: int) -> None:
-    """pred: cuda float32 tensor with one row of >= nx + m values per problem, ld apart."""
+    """pred: cuda float32 tensor with one row of ld >= nx + m values per problem."""
+    _check_rows(pred, len(batch.works), ld)
     _check(load().sos_batch_warm_start(batch.handle, _dev(pred), int(ld)), None)
 
 
 def sos_batch_export_solutions(batch: Batch, out, ld: int) -> None:
+    _check_rows(out, len(batch.works), ld)
     _check(load().sos_batch_export_solutions(batch.handle, _dev(out), int(ld)), None)
 
 

@@ -119,7 +119,8 @@ struct sos_batch {
     unsigned long long *d_ts = nullptr;   // wall-clock stamps of the solve and polish kernels
     double last_ms = 0.0, phase_ms[2] = {0.0, 0.0};
     bool use_graph = true;
-    int warm_eig = 1, lds_budget = 0;
+    int warm_eig = 1, lds_budget = 0, eig_wave = 1;
+    int gs_bucket[7] = {16, 16, 16, 16, 16, 16, 16};
     sos_settings st{};
 };
 
@@ -494,7 +495,9 @@ RunParams single_params(sos_work *w, int mode, int iters, int min_iters, double 
     rp.eig_ld = w->eig_ld;
     rp.max_sweeps = 60;
     rp.warm_eig = 1;
+    rp.eig_wave = 1;
     rp.lds_budget = kLdsBudget;
+    for (int i = 0; i < 7; ++i) rp.gs_bucket[i] = 16;
     return rp;
 }
 
@@ -526,6 +529,10 @@ void read_info(sos_work *w, const double *o, sos_info *info, int iters, int poli
     info->setup_ms = w->setup_ms;
     info->solve_ms = w->last_ms;
     info->eig_sweeps = o[SOS_OUT_SWEEPS];
+    const double khz = wall_clock_khz();
+    info->affine_ms = o[SOS_OUT_T_AFFINE] / khz;
+    info->eig_ms = o[SOS_OUT_T_EIG] / khz;
+    info->resid_ms = o[SOS_OUT_T_RES] / khz;
 }
 
 template <typename F>
@@ -826,8 +833,18 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         B->max_sweeps = (int)json_num(schedule_json, "max_sweeps", 60);
         B->use_graph = json_num(schedule_json, "use_graph", 1) != 0.0;
         B->warm_eig = (int)json_num(schedule_json, "warm_eig", 1);
-        B->lds_budget = (int)(json_num(schedule_json, "lds_kb", kLdsBudget / 1024.0) * 1024.0);
+        B->eig_wave = (int)json_num(schedule_json, "eig_wave", 1);
+        // LDS per workgroup: what wg_per_cu resident workgroups can share (160 KiB per CU, less
+        // about 10 KiB of static LDS each), unless the schedule says otherwise
+        const double lds_share = std::min<double>(kLdsBudget, 163840.0 / B->wg_per_cu - 10240.0);
+        B->lds_budget = (int)(json_num(schedule_json, "lds_kb", lds_share / 1024.0) * 1024.0);
         if (B->lds_budget < 0 || B->lds_budget > kLdsBudget) throw Status(SOS_E_INVAL, "schedule lds_kb out of range");
+        static const char *gs_keys[7] = {"gs_n32", "gs_n64", "gs_n96", "gs_n128", "gs_n192", "gs_n256", "gs_big"};
+        for (int i = 0; i < 7; ++i) {
+            B->gs_bucket[i] = (int)json_num(schedule_json, gs_keys[i], 16);
+            if (B->gs_bucket[i] != 8 && B->gs_bucket[i] != 16 && B->gs_bucket[i] != 32)
+                throw Status(SOS_E_INVAL, "schedule lanes per pair must be 8, 16 or 32");
+        }
         if (B->threads < 64 || B->threads > 1024 || (B->threads & (B->threads - 1)))
             throw Status(SOS_E_INVAL, "schedule block_threads must be a power of two in 64..1024");
         if (B->wg_per_cu < 1 || B->wg_per_cu > 16) throw Status(SOS_E_INVAL, "schedule wg_per_cu must be 1..16");
@@ -899,7 +916,9 @@ static RunParams batch_params(sos_batch *B, int mode, int iters, int min_iters, 
     rp.eig_ld = B->eig_ld;
     rp.max_sweeps = B->max_sweeps;
     rp.warm_eig = B->warm_eig;
+    rp.eig_wave = B->eig_wave;
     rp.lds_budget = B->lds_budget;
+    for (int i = 0; i < 7; ++i) rp.gs_bucket[i] = B->gs_bucket[i];
     return rp;
 }
 
@@ -993,7 +1012,7 @@ int sos_batch_warm_start(sos_batch *B, const float *pred_dev, int64_t ld) {
             hip_check(hipStreamSynchronize(w->stream), "sync");
         }
         RunParams rp = batch_params(B, RUN_SOLVE, 0, 0, B->st.tol);
-        if (sos_launch_warm_start(B->fp64, B->threads, rp, pred_dev, (long long)ld, B->stream))
+        if (sos_launch_warm_start(B->fp64, B->threads, B->grid, rp, pred_dev, (long long)ld, B->stream))
             throw Status(SOS_E_HIP, "warm start launch failed");
         hip_check(hipStreamSynchronize(B->stream), "sync");
         for (sos_work *w : B->probs) w->active64 = B->fp64 != 0;

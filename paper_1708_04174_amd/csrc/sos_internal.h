@@ -59,7 +59,7 @@ struct ProbDesc {
 
 enum {
     SOS_OUT_STATUS = 0, SOS_OUT_ITERS, SOS_OUT_POBJ, SOS_OUT_DOBJ, SOS_OUT_RP, SOS_OUT_RD, SOS_OUT_GAP,
-    SOS_OUT_TAU, SOS_OUT_KAPPA, SOS_OUT_CX, SOS_OUT_BY, SOS_OUT_TOTAL, SOS_OUT_SWEEPS, SOS_OUT_N
+    SOS_OUT_TAU, SOS_OUT_KAPPA, SOS_OUT_CX, SOS_OUT_BY, SOS_OUT_TOTAL, SOS_OUT_SWEEPS, SOS_OUT_T_AFFINE, SOS_OUT_T_EIG, SOS_OUT_T_RES, SOS_OUT_N
 };
 
 enum { RUN_STEP = 0, RUN_SOLVE = 1 };
@@ -82,9 +82,12 @@ struct RunParams {
     int max_sweeps;
     int warm_eig;           // start each block's Jacobi sweeps from the previous iteration's eigenvectors
     int lds_budget;         // dynamic LDS bytes the launch may use
-    int lds_mat_off, lds_nmax, lds_nmax_g;   // filled in by the launcher
+    int eig_wave;           // 1: blocks that fit in LDS use the one-wavefront eigensolver
+    int lds_mat_off, lds_nmax, lds_nmax_g, lpj_nmax;   // filled in by the launcher
     int accumulate;         // 0: out[TOTAL] = iterations of this launch; 1: out[TOTAL] += them, and the
                             //    iteration budget is iters - out[TOTAL] (at least min_iters)
+    int gs_bucket[7];       // lanes per Jacobi column pair (8, 16 or 32) by block-size bucket:
+                            // N < 32, < 64, < 96, < 128, < 192, < 256, >= 256
     int stall_checks;       // > 0: stop a problem whose residual missed 0.9 x its best this many checks in a row
     unsigned long long *ts; // optional [start, end] wall-clock stamps of the launch (min / max over workgroups)
 };
@@ -95,5 +98,7 @@ int sos_launch_reset(int *counter, void *stream, unsigned long long *ts = nullpt
 int sos_launch_cast_state(const ProbDesc *probs_dev, const int *ids, int count, int to64, void *stream,
                           int max_len);
 int sos_launch_reset_state(const ProbDesc *probs_dev, int count, int max_len, void *stream);
-int sos_launch_warm_start(int fp64, int threads, const RunParams &rp, const float *pred, long long ld, void *stream);
+// grid: the number of workgroups whose scratch areas (work_stride, eig_stride apart) exist
+int sos_launch_warm_start(int fp64, int threads, int grid, const RunParams &rp, const float *pred, long long ld,
+                          void *stream);
 int sos_launch_export(int fp64, const ProbDesc *probs, int count, float *out, long long ld, int max_len, void *stream);

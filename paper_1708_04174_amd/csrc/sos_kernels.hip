@@ -25,6 +25,14 @@
 
 namespace {
 
+// Pointer to LDS (address space 3).  Passing LDS buffers with this type lets the compiler
+// emit LDS instructions; through a generic pointer it has to use flat accesses, which
+// take the vector-memory path and are several times slower for LDS data.
+template <typename T> struct Lds { typedef __attribute__((address_space(3))) T type; };
+template <typename T> __device__ __forceinline__ typename Lds<T>::type *as_lds(void *p) {
+    return (typename Lds<T>::type *)(p);
+}
+
 template <typename T> struct TS;
 template <> struct TS<double> {
     __device__ static double *u(const ProbDesc &P) { return P.u64; }
@@ -139,7 +147,7 @@ __device__ void chol_solve_wave(const double *__restrict__ Lcol, const double *_
 // accumulates in (the storage type; a variant with FP64 arithmetic on FP32 storage
 // left the FP32 residual floor unchanged, since the floor comes from the stored iterate).
 template <typename T, int NT, typename AT>
-__device__ void affine_phase(const ProbDesc &P, const RunParams &rp, AT *__restrict__ wy, AT *__restrict__ wx,
+__device__ __noinline__ void affine_phase(const ProbDesc &P, const RunParams &rp, AT *__restrict__ wy, AT *__restrict__ wx,
                              double *s_z, double *s_red) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     constexpr int NW = NT / 64;
@@ -275,9 +283,11 @@ __device__ __forceinline__ void rr_pair(int r, int kk, int M, int &p, int &q) {
     if (kk == 0) {
         p = M - 1;
         q = r;
-    } else {
-        p = (r + kk) % (M - 1);
-        q = (r - kk + (M - 1)) % (M - 1);
+    } else {   // (r + kk) mod (M - 1) and (r - kk) mod (M - 1), with 0 <= r < M - 1, 0 < kk < M / 2
+        p = r + kk;
+        if (p >= M - 1) p -= M - 1;
+        q = r - kk;
+        if (q < 0) q += M - 1;
     }
     if (p > q) {
         const int t = p;
@@ -286,9 +296,17 @@ __device__ __forceinline__ void rr_pair(int r, int kk, int M, int &p, int &q) {
     }
 }
 
+// lanes per column pair for a block of size N: the schedule's choice for N's bucket
+// (buckets N < 32, 64, 96, 128, 192, 256, and above)
+__device__ __forceinline__ int lanes_per_pair(const RunParams &rp, int N) {
+    const int b = N < 32 ? 0 : N < 64 ? 1 : N < 96 ? 2 : N < 128 ? 3 : N < 192 ? 4 : N < 256 ? 5 : 6;
+    const int g = rp.gs_bucket[b];
+    return (g == 8 || g == 32) ? g : 16;
+}
+
 struct EigScratch {
-    int *s_flag;
-    int *s_sweeps;    // Jacobi sweeps run (diagnostic)
+    typename Lds<int>::type *s_flag;
+    typename Lds<int>::type *s_sweeps;    // Jacobi sweeps run (diagnostic)
     double *s_red;
 };
 
@@ -313,15 +331,14 @@ __device__ __forceinline__ T group_allsum(T x) {
 
 // One-sided Jacobi rotation of the column pair (p, q) of G (and of V) by a group of GS
 // lanes; makes g_p and g_q orthogonal.  Returns true if a rotation was applied.
-template <typename T, int GS>
-__device__ __forceinline__ bool os_rotate_pair(T *__restrict__ G, int ldg, T *__restrict__ V, int ldv, int N, int p,
-                                               int q, T tol, T atol) {
-    constexpr int RPL = 256 / GS;   // rows per lane held in registers (N <= 256)
+template <typename T, int GS, typename GP, typename VP>
+__device__ __forceinline__ bool os_rotate_pair(GP G, int ldg, VP V, int ldv, int N, int p, int q, T tol, T atol) {
+    constexpr int RPL = 8;          // rows per lane held in registers (N <= 8 GS); larger N: two passes
     const int gl = threadIdx.x & (GS - 1);
-    T *gp = G + (long long)p * ldg, *gq = G + (long long)q * ldg;
-    T *vp = V + (long long)p * ldv, *vq = V + (long long)q * ldv;
+    GP gp = G + (long long)p * ldg, gq = G + (long long)q * ldg;
+    VP vp = V + (long long)p * ldv, vq = V + (long long)q * ldv;
     T al = 0, be = 0, ga = 0;
-    if (N <= 256) {
+    if (N <= RPL * GS) {
         T xp[RPL], xq[RPL];
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
@@ -389,10 +406,10 @@ __device__ __forceinline__ bool os_rotate_pair(T *__restrict__ G, int ldg, T *__
 // barrier per round.  With a cached V from the previous ADMM iteration (warm) the sweeps
 // start from G = W V, which is nearly orthogonal once the iterates settle.
 // G, V: column-major N x N (column j at j*ld), in LDS or global scratch; Tm: N x N global.
-template <typename T, int NT>
-__device__ void project_block(T *__restrict__ vs, T *__restrict__ us, int N, T *__restrict__ Vs, bool warm,
-                              T *__restrict__ G, T *__restrict__ V, int ld, T *__restrict__ Tm, T *s_sig,
-                              const EigScratch &sc, int max_sweeps) {
+template <typename T, int NT, typename GP, typename VP>
+__device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ us, int N, T *__restrict__ Vs, bool warm, GP G,
+                              VP V, int ld, T *__restrict__ Tm, typename Lds<T>::type *s_sig, const EigScratch &sc,
+                              int max_sweeps, int gs = 16) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     constexpr int NW = NT / 64;
     if (N == 1) {
@@ -464,15 +481,37 @@ __device__ void project_block(T *__restrict__ vs, T *__restrict__ us, int N, T *
         if (tid == 0) *sc.s_flag = 0;
         __syncthreads();
         int rotated = 0;
-        constexpr int GS = 16;                       // lanes per column pair
-        const int grp = tid / GS;
-        for (int r = 0; r < M - 1; ++r) {
-            for (int kk = grp; kk < H; kk += NT / GS) {
-                int p, q;
-                rr_pair(r, kk, M, p, q);
-                if (q < N && os_rotate_pair<T, GS>(G, ld, V, ld, N, p, q, tol, atol)) rotated = 1;
+        // lanes per column pair: a tile choice per block-size bucket (autotuned)
+        if (gs == 8) {
+            const int grp = tid / 8;
+            for (int r = 0; r < M - 1; ++r) {
+                for (int kk = grp; kk < H; kk += NT / 8) {
+                    int p, q;
+                    rr_pair(r, kk, M, p, q);
+                    if (q < N && os_rotate_pair<T, 8, GP, VP>(G, ld, V, ld, N, p, q, tol, atol)) rotated = 1;
+                }
+                __syncthreads();
             }
-            __syncthreads();
+        } else if (gs == 32) {
+            const int grp = tid / 32;
+            for (int r = 0; r < M - 1; ++r) {
+                for (int kk = grp; kk < H; kk += NT / 32) {
+                    int p, q;
+                    rr_pair(r, kk, M, p, q);
+                    if (q < N && os_rotate_pair<T, 32, GP, VP>(G, ld, V, ld, N, p, q, tol, atol)) rotated = 1;
+                }
+                __syncthreads();
+            }
+        } else {
+            const int grp = tid / 16;
+            for (int r = 0; r < M - 1; ++r) {
+                for (int kk = grp; kk < H; kk += NT / 16) {
+                    int p, q;
+                    rr_pair(r, kk, M, p, q);
+                    if (q < N && os_rotate_pair<T, 16, GP, VP>(G, ld, V, ld, N, p, q, tol, atol)) rotated = 1;
+                }
+                __syncthreads();
+            }
         }
         if (rotated) *sc.s_flag = 1;
         __syncthreads();
@@ -538,9 +577,190 @@ __device__ void project_block(T *__restrict__ vs, T *__restrict__ us, int N, T *
     __syncthreads();
 }
 
+// ----------------------------------------------------------------------------- PSD projection, one wavefront
+// Leading dimension for a column-major N x N matrix in LDS that one wavefront walks lane
+// per column: ld = 1 (mod 32 banks), so lanes reading element i of distinct columns hit
+// distinct banks.
+__host__ __device__ __forceinline__ int lpj_ld(int N, int elem_bytes) {
+    const int q = elem_bytes == 4 ? 32 : 16;
+    return q * ((N - 1 + q - 1) / q) + 1;
+}
+
+__device__ __forceinline__ void wave_fence_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Same projection as project_block, run by ONE wavefront: one lane owns one column pair
+// per round (several for N > 128), computes the three inner products serially and
+// rotates its two columns of G and V.  No workgroup barrier and no cross-lane reduction
+// inside the sweeps: lanes only share LDS, ordered by wavefront fences between rounds.
+// G, V: column-major in LDS with leading dimension ld = lpj_ld(N); Tm: N x N global temp.
+template <typename T>
+__device__ __noinline__ void project_block_wave(T *__restrict__ vs, T *__restrict__ us, int N, T *__restrict__ Vs, bool warm,
+                                   typename Lds<T>::type *G, typename Lds<T>::type *V, int ld, T *__restrict__ Tm,
+                                   typename Lds<T>::type *sig, int *sweeps, int max_sweeps) {
+    typedef typename Lds<T>::type LT;
+    const int lane = threadIdx.x & 63;
+    if (N == 1) {
+        if (lane == 0) {
+            const T w = vs[0];
+            const T x = w > (T)0 ? w : (T)0;
+            us[0] = x;
+            vs[0] = x - w;
+            if (Vs) Vs[0] = (T)1;
+        }
+        wave_fence_sync();
+        return;
+    }
+    double fro2 = 0.0;
+    for (int idx = lane; idx < N * N; idx += 64) {
+        const int j = idx / N, i = idx - (idx / N) * N;
+        const int a = i > j ? i : j, bb = i > j ? j : i;
+        const T x = vs[svec_idx(a, bb, N)];
+        fro2 += (double)x * (double)x;
+        if (warm) {
+            Tm[j * N + i] = x;
+            V[j * ld + i] = Vs[j * N + i];
+        } else {
+            G[j * ld + i] = x;
+            V[j * ld + i] = (i == j) ? (T)1 : (T)0;
+        }
+    }
+    fro2 = wave_allsum(fro2);
+    wave_fence_sync();
+    if (warm) {
+        // G = W V_prev, a 4 x 4 tile per lane
+        const int nt = (N + 3) >> 2;
+        for (int t = lane; t < nt * nt; t += 64) {
+            const int i0 = (t / nt) * 4, j0 = (t - (t / nt) * nt) * 4;
+            T acc[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+            for (int kk = 0; kk < N; ++kk) {
+                T wa[4], vb[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) wa[a] = (i0 + a < N) ? Tm[kk * N + i0 + a] : (T)0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) vb[b] = (j0 + b < N) ? V[(j0 + b) * ld + kk] : (T)0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] += wa[a] * vb[b];
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (i0 + a < N && j0 + b < N) G[(j0 + b) * ld + i0 + a] = acc[a][b];
+        }
+        wave_fence_sync();
+    }
+    const T tol = (T)(16.0 * TS<T>::eps);
+    const T atol = (T)(TS<T>::eps * sqrt(fro2));
+    const int M = N + (N & 1);
+    const int H = M / 2;
+    int nsw = 0;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        int rotated = 0;
+        for (int r = 0; r < M - 1; ++r) {
+            for (int kk = lane; kk < H; kk += 64) {
+                int p, q;
+                rr_pair(r, kk, M, p, q);
+                if (q >= N) continue;
+                LT *gp = G + p * ld, *gq = G + q * ld;
+                T al = 0, be = 0, ga = 0;
+#pragma unroll 4
+                for (int i = 0; i < N; ++i) {
+                    const T a = gp[i], b = gq[i];
+                    al += a * a;
+                    be += b * b;
+                    ga += a * b;
+                }
+                if (!(fabs(ga) > tol * sqrt(al * be)) || !(fabs(ga) > atol * sqrt(al > be ? al : be))) continue;
+                const T ze = (be - al) / ((T)2 * ga);
+                const T tt = (ze >= (T)0 ? (T)1 : (T)-1) / (fabs(ze) + sqrt((T)1 + ze * ze));
+                const T cc = (T)1 / sqrt((T)1 + tt * tt), ss = cc * tt;
+                LT *vp = V + p * ld, *vq = V + q * ld;
+#pragma unroll 4
+                for (int i = 0; i < N; ++i) {
+                    const T a = gp[i], b = gq[i];
+                    gp[i] = cc * a - ss * b;
+                    gq[i] = ss * a + cc * b;
+                    const T c = vp[i], d = vq[i];
+                    vp[i] = cc * c - ss * d;
+                    vq[i] = ss * c + cc * d;
+                }
+                rotated = 1;
+            }
+            wave_fence_sync();
+        }
+        ++nsw;
+        if (!__any(rotated)) break;
+    }
+    if (lane == 0) *sweeps += nsw;
+    for (int j = lane; j < N; j += 64) {
+        T s = 0;
+        const LT *gj = G + j * ld;
+        for (int i = 0; i < N; ++i) s += gj[i] * gj[i];
+        sig[j] = sqrt(s);
+    }
+    wave_fence_sync();
+    // u = lower((W + V Sigma V^T) / 2), v = u - w, 4 x 4 tiles on and below the diagonal
+    const int nt = (N + 3) >> 2;
+    const int ntri = nt * (nt + 1) / 2;
+    for (int t = lane; t < ntri; t += 64) {
+        int ta = 0, rem = t;
+        while (rem > ta) {
+            rem -= ta + 1;
+            ++ta;
+        }
+        const int a0 = ta * 4, b0 = rem * 4;
+        T acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+        for (int j = 0; j < N; ++j) {
+            const T sg = sig[j];
+            T va[4], vb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) va[a] = (a0 + a < N) ? V[j * ld + a0 + a] * sg : (T)0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) vb[b] = (b0 + b < N) ? V[j * ld + b0 + b] : (T)0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] += va[a] * vb[b];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = a0 + a, j = b0 + b;
+                if (i < N && j <= i) {
+                    const int s = svec_idx(i, j, N);
+                    const T w = vs[s];
+                    const T x = (T)0.5 * (w + acc[a][b]);
+                    us[s] = x;
+                    vs[s] = x - w;
+                }
+            }
+    }
+    if (Vs)
+        for (int idx = lane; idx < N * N; idx += 64) {
+            const int j = idx / N, i = idx - (idx / N) * N;
+            Vs[j * N + i] = V[j * ld + i];
+        }
+    wave_fence_sync();
+}
+
 // ----------------------------------------------------------------------------- residuals (FP64)
 template <typename T, int NT>
-__device__ int residual_phase(const ProbDesc &P, double tol, double *s_red, int iters_done, double *res_max = nullptr) {
+__device__ __noinline__ int residual_phase(const ProbDesc &P, double tol, double *s_red, int iters_done, double *res_max = nullptr) {
     const int tid = threadIdx.x;
     const int m = P.m, nx = P.nx;
     const T *__restrict__ u = TS<T>::u(P);
@@ -612,8 +832,11 @@ __device__ int residual_phase(const ProbDesc &P, double tol, double *s_red, int 
 }
 
 // ----------------------------------------------------------------------------- persistent driver
+// launch bounds: at least 2 waves per SIMD (the second argument is waves per execution
+// unit), i.e. at most 256 VGPRs, so that two or more workgroups (problems) can share a CU
+// and hide each other's latency
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void admm_persistent(RunParams rp) {
+__global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
     __shared__ int s_idx;
     __shared__ int s_flag;
     __shared__ int s_sweeps;
@@ -622,12 +845,15 @@ __global__ __launch_bounds__(NT) void admm_persistent(RunParams rp) {
     extern __shared__ char dyn_lds[];
     // dynamic LDS: sigma (eig_ld values), then G and V of blocks with N <= rp.lds_nmax,
     // or G alone for blocks with N <= rp.lds_nmax_g
-    T *s_sig = reinterpret_cast<T *>(dyn_lds);
-    T *s_mat = reinterpret_cast<T *>(dyn_lds + rp.lds_mat_off);
+    typename Lds<T>::type *s_sig = as_lds<T>(dyn_lds);
+    typename Lds<T>::type *s_mat = as_lds<T>(dyn_lds + rp.lds_mat_off);
 
     char *wbase = reinterpret_cast<char *>(rp.work) + (long long)blockIdx.x * rp.work_stride;
     char *ebase = reinterpret_cast<char *>(rp.eig) + (long long)blockIdx.x * rp.eig_stride;
-    EigScratch sc{&s_flag, &s_sweeps, s_red};
+    EigScratch sc;
+    sc.s_flag = as_lds<int>((void *)&s_flag);
+    sc.s_sweeps = as_lds<int>((void *)&s_sweeps);
+    sc.s_red = s_red;
     if (rp.ts && threadIdx.x == 0) atomicMin(&rp.ts[0], (unsigned long long)wall_clock64());
 
     for (;;) {
@@ -649,6 +875,7 @@ __global__ __launch_bounds__(NT) void admm_persistent(RunParams rp) {
 
         int it = 0;
         int status = 0;
+        unsigned long long t_aff = 0, t_eig = 0, t_res = 0, t0 = 0;   // wall-clock ticks by phase
         // iteration budget: in an accumulating (second) phase, what the first phase left over
         int cap = rp.iters;
         if (rp.accumulate) {
@@ -659,32 +886,48 @@ __global__ __launch_bounds__(NT) void admm_persistent(RunParams rp) {
         int since_best = 0;
         bool stalled = false;
         while (it < cap) {
+            t0 = wall_clock64();
             affine_phase<T, NT, T>(P, rp, wy, wx, s_z, s_red);
+            const unsigned long long t1 = wall_clock64();
+            t_aff += t1 - t0;
             long long voff = 0;
             for (int bk = 0; bk < P.nblk; ++bk) {
                 const int off = P.blk_off[bk];
                 const int N = P.blk_N[bk];
-                T *EG, *EV;
-                const int ld = N;
-                if (N <= rp.lds_nmax) {
-                    EG = s_mat;
-                    EV = s_mat + (long long)N * N;
-                } else if (N <= rp.lds_nmax_g) {
-                    EG = s_mat;
-                    EV = Tm + (long long)P.nmax * P.nmax;
-                } else {
-                    EG = Tm + (long long)P.nmax * P.nmax;
-                    EV = EG + (long long)P.nmax * P.nmax;
+                if (N <= rp.lpj_nmax) {
+                    // one wavefront, lane per column pair, G and V in LDS
+                    if ((threadIdx.x >> 6) == 0) {
+                        const int ldp = lpj_ld(N, (int)sizeof(T));
+                        project_block_wave<T>(v + off, u + off, N, rp.warm_eig ? vstore + voff : nullptr,
+                                              rp.warm_eig && warm, s_mat, s_mat + (long long)N * ldp, ldp, Tm, s_sig,
+                                              &s_sweeps, rp.max_sweeps);
+                    }
+                    __syncthreads();
+                    voff += (long long)N * N;
+                    continue;
                 }
-                project_block<T, NT>(v + off, u + off, N, rp.warm_eig ? vstore + voff : nullptr,
-                                     rp.warm_eig && warm, EG, EV, ld, Tm, s_sig, sc, rp.max_sweeps);
+                const int ld = N;
+                T *vc = rp.warm_eig ? vstore + voff : nullptr;
+                const bool wm = rp.warm_eig && warm;
+                const int gs = lanes_per_pair(rp, N);
+                T *g1 = Tm + (long long)P.nmax * P.nmax, *g2 = g1 + (long long)P.nmax * P.nmax;
+                if (N <= rp.lds_nmax)        // G and V in LDS
+                    project_block<T, NT>(v + off, u + off, N, vc, wm, s_mat, s_mat + (long long)N * N, ld, Tm, s_sig,
+                                         sc, rp.max_sweeps, gs);
+                else if (N <= rp.lds_nmax_g)  // G in LDS, V in global scratch
+                    project_block<T, NT>(v + off, u + off, N, vc, wm, s_mat, g1, ld, Tm, s_sig, sc, rp.max_sweeps, gs);
+                else                          // both in global scratch
+                    project_block<T, NT>(v + off, u + off, N, vc, wm, g1, g2, ld, Tm, s_sig, sc, rp.max_sweeps, gs);
                 voff += (long long)N * N;
             }
             warm = rp.warm_eig != 0;
             ++it;
+            const unsigned long long t2 = wall_clock64();
+            t_eig += t2 - t1;
             if (rp.mode == RUN_SOLVE && it >= rp.min_iters && (it % rp.check_every == 0 || it == cap)) {
                 double mx = INFINITY;
                 status = residual_phase<T, NT>(P, rp.tol, s_red, it, &mx);
+                t_res += wall_clock64() - t2;
                 if (status) break;
                 // a phase that stops improving hands over (the FP32 phase of the mixed form):
                 // stalled once stall_checks checks in a row missed 0.9 x the best residual
@@ -704,6 +947,9 @@ __global__ __launch_bounds__(NT) void admm_persistent(RunParams rp) {
             if (rp.mode == RUN_SOLVE && status == 0 && !stalled && threadIdx.x == 0) P.out[SOS_OUT_STATUS] = 4;
         }
         if (threadIdx.x == 0) {
+            P.out[SOS_OUT_T_AFFINE] = (double)t_aff;
+            P.out[SOS_OUT_T_EIG] = (double)t_eig;
+            P.out[SOS_OUT_T_RES] = (double)t_res;
             P.out[SOS_OUT_SWEEPS] = (it > 0 && P.nblk > 0) ? (double)s_sweeps / ((double)it * P.nblk) : 0.0;
             P.out[SOS_OUT_TOTAL] = (rp.accumulate ? P.out[SOS_OUT_TOTAL] : 0.0) + it;
             if (it > 0) P.tk[2] = rp.warm_eig ? 1.0 : 0.0;
@@ -715,23 +961,27 @@ __global__ __launch_bounds__(NT) void admm_persistent(RunParams rp) {
 
 // Learned warm start: from a predicted (xi, y) (FP32 rows, internal layout), set
 //   u = (P_K(xi), y, 1),  v = (P_{K*}(c - A^T y), 0, 0)
-// for every problem of a batch; one workgroup per problem.
+// for every problem of a batch.  Launched on the batch's persistent grid (whose
+// per-workgroup scratch areas exist), each workgroup takes problems blockIdx.x,
+// blockIdx.x + gridDim.x, ...
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void warm_start_kernel(RunParams rp, const float *__restrict__ pred, long long ld) {
     __shared__ int s_flag;
     __shared__ int s_sweeps;
     __shared__ double s_red[4 * (NT / 64)];
     extern __shared__ char dyn_lds[];
-    T *s_sig = reinterpret_cast<T *>(dyn_lds);
-    T *s_mat = reinterpret_cast<T *>(dyn_lds + rp.lds_mat_off);
-    const int p = blockIdx.x;
-    if (p >= rp.count) return;
-    const ProbDesc &P = rp.probs[p];
+    typename Lds<T>::type *s_sig = as_lds<T>(dyn_lds);
+    typename Lds<T>::type *s_mat = as_lds<T>(dyn_lds + rp.lds_mat_off);
     char *wbase = reinterpret_cast<char *>(rp.work) + (long long)blockIdx.x * rp.work_stride;
     char *ebase = reinterpret_cast<char *>(rp.eig) + (long long)blockIdx.x * rp.eig_stride;
     T *wx = reinterpret_cast<T *>(wbase);
     T *Tm = reinterpret_cast<T *>(ebase);
-    EigScratch sc{&s_flag, &s_sweeps, s_red};
+    EigScratch sc;
+    sc.s_flag = as_lds<int>((void *)&s_flag);
+    sc.s_sweeps = as_lds<int>((void *)&s_sweeps);
+    sc.s_red = s_red;
+    for (int p = blockIdx.x; p < rp.count; p += gridDim.x) {
+    const ProbDesc &P = rp.probs[p];
     T *u = TS<T>::u(P);
     T *v = TS<T>::v(P);
     const float *xs = pred + (long long)p * ld;
@@ -755,20 +1005,26 @@ __global__ __launch_bounds__(NT) void warm_start_kernel(RunParams rp, const floa
         const int off = P.blk_off[bk];
         const int N = P.blk_N[bk];
         const int ns = N * (N + 1) / 2;
-        T *EG, *EV;
-        if (N <= rp.lds_nmax) {
-            EG = s_mat;
-            EV = s_mat + (long long)N * N;
-        } else if (N <= rp.lds_nmax_g) {
-            EG = s_mat;
-            EV = Tm + (long long)P.nmax * P.nmax;
-        } else {
-            EG = Tm + (long long)P.nmax * P.nmax;
-            EV = EG + (long long)P.nmax * P.nmax;
-        }
+        T *g1 = Tm + (long long)P.nmax * P.nmax, *g2 = g1 + (long long)P.nmax * P.nmax;
         for (int pass = 0; pass < 2; ++pass) {
             T *blk = (pass == 0 ? u : v) + off;   // projected in place via the scratch wx
-            project_block<T, NT>(blk, wx, N, nullptr, false, EG, EV, N, Tm, s_sig, sc, rp.max_sweeps);
+            if (N <= rp.lpj_nmax) {
+                if ((threadIdx.x >> 6) == 0) {
+                    const int ldp = lpj_ld(N, (int)sizeof(T));
+                    project_block_wave<T>(blk, wx, N, nullptr, false, s_mat, s_mat + (long long)N * ldp, ldp, Tm, s_sig,
+                                          &s_sweeps, rp.max_sweeps);
+                }
+                __syncthreads();
+            } else if (N <= rp.lds_nmax) {
+                project_block<T, NT>(blk, wx, N, nullptr, false, s_mat, s_mat + (long long)N * N, N, Tm, s_sig, sc,
+                                     rp.max_sweeps, lanes_per_pair(rp, N));
+            } else if (N <= rp.lds_nmax_g) {
+                project_block<T, NT>(blk, wx, N, nullptr, false, s_mat, g1, N, Tm, s_sig, sc, rp.max_sweeps,
+                                     lanes_per_pair(rp, N));
+            } else {
+                project_block<T, NT>(blk, wx, N, nullptr, false, g1, g2, N, Tm, s_sig, sc, rp.max_sweeps,
+                                     lanes_per_pair(rp, N));
+            }
             for (int s = tid; s < ns; s += NT) blk[s] = wx[s];
             __syncthreads();
         }
@@ -777,6 +1033,8 @@ __global__ __launch_bounds__(NT) void warm_start_kernel(RunParams rp, const floa
         P.tk[0] = 1.0;
         P.tk[1] = 0.0;
         P.tk[2] = 0.0;
+    }
+    __syncthreads();
     }
 }
 
@@ -846,7 +1104,8 @@ __global__ void reset_state(const ProbDesc *probs, int count) {
 // Dynamic LDS layout for element type T: sigma, then G and V (both N x N) for blocks up to
 // lds_nmax, or G alone for blocks up to lds_nmax_g; larger blocks work in global scratch.
 template <typename T>
-void lds_layout(int eig_ld, int lds_budget, int &mat_off, int &lds_nmax, int &lds_nmax_g, size_t &bytes) {
+void lds_layout(int eig_ld, int lds_budget, int &mat_off, int &lds_nmax, int &lds_nmax_g, size_t &bytes,
+                int use_lpj, int &lpj_nmax) {
     size_t off = sizeof(T) * (size_t)(eig_ld + 1);
     off = (off + 15) & ~(size_t)15;
     mat_off = (int)off;
@@ -858,13 +1117,21 @@ void lds_layout(int eig_ld, int lds_budget, int &mat_off, int &lds_nmax, int &ld
     const size_t need2 = lds_nmax ? off + sizeof(T) * 2 * (size_t)lds_nmax * lds_nmax : off;
     const size_t need1 = lds_nmax_g ? off + sizeof(T) * (size_t)lds_nmax_g * lds_nmax_g : off;
     bytes = need2 > need1 ? need2 : need1;
+    // one-wavefront form: G and V with the padded leading dimension
+    lpj_nmax = 0;
+    if (use_lpj)
+        for (int N = eig_ld; N >= 1 && !lpj_nmax; --N)
+            if ((long long)(off + sizeof(T) * 2 * (size_t)N * lpj_ld(N, (int)sizeof(T))) <= lds_budget) lpj_nmax = N;
+    const size_t need3 = lpj_nmax ? off + sizeof(T) * 2 * (size_t)lpj_nmax * lpj_ld(lpj_nmax, (int)sizeof(T)) : off;
+    if (need3 > bytes) bytes = need3;
 }
 
 template <typename T, int NT>
 int launch_t(int grid, const RunParams &rp_in, hipStream_t st) {
     RunParams rp = rp_in;
     size_t lds = 0;
-    lds_layout<T>(rp.eig_ld, rp.lds_budget, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds);
+    lds_layout<T>(rp.eig_ld, rp.lds_budget, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds, rp.eig_wave,
+                  rp.lpj_nmax);
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&admm_persistent<T, NT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -927,20 +1194,23 @@ int sos_launch_reset_state(const ProbDesc *probs_dev, int count, int max_len, vo
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
-int sos_launch_warm_start(int fp64, int threads, const RunParams &rp_in, const float *pred, long long ld, void *stream) {
+int sos_launch_warm_start(int fp64, int threads, int grid, const RunParams &rp_in, const float *pred, long long ld,
+                          void *stream) {
     RunParams rp = rp_in;
+    if (grid < 1) return -1;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     size_t lds = 0;
     (void)hipGetLastError();
 #define SOS_WS(TT, NTT)                                                                                          \
     {                                                                                                           \
-        lds_layout<TT>(rp.eig_ld, rp.lds_budget, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds);              \
+        lds_layout<TT>(rp.eig_ld, rp.lds_budget, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds, rp.eig_wave,  \
+                       rp.lpj_nmax);                                                                            \
         if (lds > 64 * 1024) {                                                                                  \
             (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&warm_start_kernel<TT, NTT>),               \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                    \
             (void)hipGetLastError();                                                                            \
         }                                                                                                       \
-        hipLaunchKernelGGL((warm_start_kernel<TT, NTT>), dim3(rp.count), dim3(NTT), lds, st, rp, pred, ld);      \
+        hipLaunchKernelGGL((warm_start_kernel<TT, NTT>), dim3(grid), dim3(NTT), lds, st, rp, pred, ld);          \
     }
     if (fp64) {
         if (threads == 256) SOS_WS(double, 256) else if (threads == 512) SOS_WS(double, 512) else if (threads == 128) SOS_WS(double, 128) else SOS_WS(double, 64)

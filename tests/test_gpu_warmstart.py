@@ -122,3 +122,54 @@ def test_learned_warm_start_gain(env):
         if inf["status"] == B.SOS_SOLVED:
             assert max(inf["res_pri"], inf["res_dual"], inf["gap"]) <= 1e-4
     assert same >= len(test) - 2
+
+
+def test_warm_start_kernel_on_more_problems_than_workgroups(env):
+    # 300 problems on a 256-workgroup grid: every workgroup takes several problems.  The
+    # state each problem gets is checked against u = (P_K(xi), y, 1), v = (P_K*(c - A^T y), 0, 0)
+    # computed on the host with LAPACK eigh.
+    B, torch = env
+    from oracle.admm import proj_psd
+    probs = [F.lyapunov(s) for s in range(300)]
+    st = B.sos_default_settings(tol=1e-4, max_iters=10)
+    works = [B.setup_problem(p, st) for p in probs]
+    bt = B.sos_batch_setup(works, '{"wg_per_cu": 1, "block_threads": 256}')
+    L = B.sos_layout_size(works[0])
+    rng = np.random.default_rng(11)
+    pred = rng.standard_normal((len(probs), L)).astype(np.float32) * 0.1
+    B.sos_batch_warm_start(bt, _dev(torch, pred), L)
+    p0 = probs[0]
+    nf, N1, N2 = p0.n_free, p0.psd_dims[0], p0.psd_dims[1]
+    nx = nf + N1 * (N1 + 1) // 2 + N2 * (N2 + 1) // 2
+
+    def lower_to_full(vec):
+        out, o = [vec[:nf]], nf
+        for N in (N1, N2):
+            M = np.zeros((N, N))
+            for j in range(N):
+                for i in range(j, N):
+                    M[i, j] = M[j, i] = vec[o]
+                    o += 1
+            out.append(M.reshape(-1, order="F"))
+        return np.concatenate(out)
+
+    for idx in (0, 137, 255, 256, 299):
+        p = probs[idx]
+        xi = lower_to_full(pred[idx, :nx].astype(np.float64))
+        y = pred[idx, nx:].astype(np.float64)
+        z = p.c - p.A.T @ y
+        z[:nf] = 0.0
+        uref, vref, o = xi.copy(), z.copy(), nf
+        for N in (N1, N2):
+            uref[o:o + N * N] = proj_psd(xi[o:o + N * N].reshape(N, N, order="F")).reshape(-1, order="F")
+            vref[o:o + N * N] = proj_psd(z[o:o + N * N].reshape(N, N, order="F")).reshape(-1, order="F")
+            o += N * N
+        u, v = B.sos_get_iterate(works[idx])
+        n, m = p.n, p.m
+        assert u[n + m] == 1.0 and v[n + m] == 0.0 and np.all(v[n:n + m] == 0.0)
+        assert np.allclose(u[n:n + m], y, atol=1e-7)
+        eu = np.linalg.norm(u[:n] - uref) / max(1.0, np.linalg.norm(uref))
+        ev = np.linalg.norm(v[:n] - vref) / max(1.0, np.linalg.norm(vref))
+        print(f"[warm] problem {idx}: |du| {eu:.1e} |dv| {ev:.1e}", flush=True)
+        assert eu < 1e-5 and ev < 1e-5
+    bt.free()
