@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--schedule", default=None)
     ap.add_argument("--train-count", type=int, default=3584)
     ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--warm-iters", type=int, default=400,
+                    help="iteration budget of the warm-started attempt; what it leaves unsolved is re-solved cold")
     ap.add_argument("--plain-sample", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -138,6 +140,7 @@ def main():
     if lyap and train_probs:
         t0 = time.perf_counter()
         X, T = [], []
+        nsolved = 0
         for i in range(0, len(train_probs), 512):
             chunk = train_probs[i:i + 512]
             tw = [B.setup_problem(p, st) for p in chunk]
@@ -145,12 +148,16 @@ def main():
             keep = [j for j, inf in enumerate(infos) if inf["status"] == B.SOS_SOLVED]
             X.append(WL.lyapunov_features([train_seeds[i + j] for j in keep]))
             T.append(sol[torch.tensor(keep, device="cuda")].contiguous())
+            nsolved = nsolved + len(keep)
             tb.free()
             for w in tw:
                 w.free()
             log(f"[bench] training data {i + len(chunk)}/{len(train_probs)}: {len(keep)} solved")
         Xtr = torch.from_numpy(np.concatenate(X)).cuda()
         Ttr = torch.cat(T).contiguous()
+        mask = W.training_mask(Ttr)
+        Xtr, Ttr = Xtr[mask].contiguous(), Ttr[mask].contiguous()
+        log(f"[bench] training set: {int(mask.sum())} of {nsolved} solved instances (norm <= 3 x median)")
         t1 = time.perf_counter()
         model = W.WarmStartModel(Xtr.shape[1], Ttr.shape[1], hidden=512, max_batch=4096, seed=0)
         losses = model.fit(Xtr, Ttr, epochs=args.epochs, batch=256, lr=1e-3, log=log)
@@ -158,6 +165,10 @@ def main():
                       "data_s": t1 - t0, "fit_s": time.perf_counter() - t1}
         log(f"[bench] model: {train_info}")
         Xte = torch.from_numpy(WL.lyapunov_features(test_seeds)).cuda()
+        st_warm = B.sos_default_settings(tol=args.tol, max_iters=args.warm_iters, check_every=10,
+                                         precision=B.SOS_FP32_MIXED, polish_iters=1)
+        warm_works = [B.setup_problem(p, st_warm) for p in probs]
+        warm_batch = B.sos_batch_setup(warm_works, sched)
 
     # ---------------------------------------------------------------- cold batched (ablation)
     def cold_step():
@@ -173,12 +184,16 @@ def main():
             "iters_mean": float(np.mean([i["iters"] for i in cinfos]))}
     log(f"[bench] cold batched: {cold}")
 
+    warm_info = {}
+
     def warm_step():
-        B.sos_batch_reset(batch)
+        B.sos_batch_reset(warm_batch)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        infos, nfb, _ = W.warm_solve(batch, model, Xte, fallback_works=works, layout=layout)
+        infos, nfb, _ = W.warm_solve(warm_batch, model, Xte, fallback_works=works, layout=layout, schedule=sched)
         torch.cuda.synchronize()
+        warm_info["first"] = [dict(i) for i in W.LAST_FIRST_PASS]
+        warm_info["fallback"] = dict(W.LAST_FALLBACK)
         return infos, (time.perf_counter() - t) * 1e3, nfb
 
     step = (lambda: warm_step()) if model is not None else (lambda: cold_step() + (0,))
@@ -193,8 +208,9 @@ def main():
         ok = sum(inf["status"] in OK_STATUS for inf in infos)
         step_ms.append(ms)
         counted.append(ok)
-        kms.append(B.sos_batch_phase_ms(batch, 0))
-        pms.append(B.sos_batch_phase_ms(batch, 1))
+        tb = warm_batch if model is not None else batch
+        kms.append(B.sos_batch_phase_ms(tb, 0))
+        pms.append(B.sos_batch_phase_ms(tb, 1))
         fbs.append(nfb)
         log(f"[bench] step {i}: {ms:.1f} ms, {ok}/{len(infos)} counted, fallbacks {nfb}, "
             f"solve kernel {kms[-1]:.1f} ms, polish kernel {pms[-1]:.1f} ms")
@@ -207,14 +223,43 @@ def main():
     solved = [inf for inf in infos if inf["status"] == 1]
     worst = max(max(i["res_pri"], i["res_dual"], i["gap"]) for i in solved) if solved else None
 
-    # roofline of the dominant kernel (the persistent FP32 solve kernel of the last step)
-    fp32_iters = [inf["iters"] - inf["polish_iters"] for inf in infos]
-    flops = float(sum(it * iter_flops(p) for it, p in zip(fp32_iters, probs)))
-    k_ms = float(kms[-1])
+    # roofline of the dominant kernel of the last step: the FP32 bulk kernel or the FP64
+    # kernel, whichever ran longer summed over the step's launches (the batched pass and,
+    # after a warm start, the cold fallback); figures per launch, averaged over those launches
+    first = warm_info.get("first") or infos
+    fb = warm_info.get("fallback") or {}
+    sched_d = json.loads(sched) if sched else {}
+    thr = int(sched_d.get("block_threads", 256))
+    l32 = [(float(kms[-1]), [inf["iters"] - inf["polish_iters"] for inf in first], list(range(len(probs))))]
+    l64 = [(float(pms[-1]), [inf["polish_iters"] for inf in first], list(range(len(probs))))]
+    if fb:
+        l32.append((fb["phase_ms"][0], [f["iters"] - f["polish_iters"] for f in fb["infos"]], fb["idx"]))
+        l64.append((fb["phase_ms"][1], [f["polish_iters"] for f in fb["infos"]], fb["idx"]))
+    if sum(x[0] for x in l32) >= sum(x[0] for x in l64):
+        kname, launches, peak = f"admm_persistent<float, {thr}>", l32, PEAK_FP32_TFLOPS
+    else:
+        kname, launches, peak = f"admm_persistent<double, {thr}>", l64, PEAK_FP64_TFLOPS
+    k_ms = float(np.mean([x[0] for x in launches]))
+    flops = float(np.mean([sum(it * iter_flops(probs[j]) for it, j in zip(x[1], x[2])) for x in launches]))
     achieved = flops / (k_ms / 1e3) / 1e12 if k_ms > 0 else None
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": None,
-                "kernel": "admm_persistent<float>", "kernel_ms": k_ms, "algorithmic_flops_per_launch": flops}
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": (achieved / peak) if achieved else None, "traffic": None,
+                "kernel": kname, "kernel_ms": k_ms, "launches_per_step": len(launches),
+                "launch_ms": [x[0] for x in launches], "algorithmic_flops_per_launch": flops,
+                "iterations_per_launch": float(np.mean([np.sum(x[1]) for x in launches]))}
+
+    # what the learned warm start gains: iterations of the warm-started pass against the
+    # cold batched solve, on the problems both solve
+    warm_gain = None
+    if model is not None:
+        both = [i for i in range(len(probs)) if cinfos[i]["status"] == 1 and first[i]["status"] == 1]
+        warm_gain = {"warm_budget": args.warm_iters, "solved_by_warm_pass": int(sum(f["status"] == 1 for f in first)),
+                     "common_solved": len(both),
+                     "cold_iters_mean": float(np.mean([cinfos[i]["iters"] for i in both])) if both else None,
+                     "warm_iters_mean": float(np.mean([first[i]["iters"] for i in both])) if both else None,
+                     "cold_iters_median": float(np.median([cinfos[i]["iters"] for i in both])) if both else None,
+                     "warm_iters_median": float(np.median([first[i]["iters"] for i in both])) if both else None}
+        log(f"[bench] warm start gain: {warm_gain}")
 
     plain = None
     if not args.no_plain:
@@ -256,6 +301,7 @@ def main():
         "cpu_baseline": cpu,
         "plain_fp64": plain,
         "batched_cold_fp32": cold,
+        "warm_start_gain": warm_gain,
         "speedup_vs_plain_fp64": (value / plain["value"]) if plain else None,
     }
     print(json.dumps(out), flush=True)

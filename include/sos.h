@@ -12,7 +12,9 @@
  *            update (the three ADMM steps of Section IV-A).
  *   affine   I + A A^T = P + A_f A_f^T with P diagonal (Proposition 1 and its
  *            weighted form in Section VI); solved with the matrix inversion lemma
- *            and a cached FP64 Cholesky of I + A_f^T P^{-1} A_f (Section IV-B).
+ *            (Section IV-B) and the FP64 inverse of I + A_f^T P^{-1} A_f, formed
+ *            once at setup from its Cholesky factor, so that each iteration's small
+ *            solve is one dense matrix-vector product.
  *
  * Conventions for every function below
  *   - Return value: SOS_OK (0) or a negative SOS_E_* code.  Nothing throws across
@@ -58,7 +60,7 @@ extern "C" {
 /* precision forms */
 #define SOS_FP64        0   /* every step in FP64 */
 #define SOS_FP32_MIXED  1   /* FP32 bulk (matvecs, eigensolves, FP32 accumulation); FP64 for the
-                               Cholesky solve, theta, tau/kappa, residuals; FP64 polish at the end */
+                               small solve with S, theta, tau/kappa, residuals; FP64 polish at the end */
 
 /* column partition of A into the diagonal part A_s and the low-rank part A_f */
 #define SOS_PART_PAPER    0  /* A_f = all free columns + every PSD column with >= 2 nonzeros (Sections IV-B, VI) */
@@ -96,7 +98,7 @@ typedef struct {
 typedef struct {
     int32_t status;          /* SOS_* status above */
     int32_t iters;           /* total iterations run (FP32 + FP64 polish) */
-    int32_t k_lowrank;       /* columns of A_f = size of the cached Cholesky factor */
+    int32_t k_lowrank;       /* columns of A_f = order of the small matrix S */
     int32_t polish_iters;    /* FP64 iterations run after the FP32 phase */
     double  pobj, dobj;      /* c^T xi / tau, b^T y / tau */
     double  res_pri, res_dual, gap;   /* |A xi - b tau|/tau/(1+|b|), |A^T y + z - c tau|/tau/(1+|c|),
@@ -114,7 +116,7 @@ int sos_default_settings(sos_settings *s);
 /* Validates the problem, folds PSD blocks to their lower triangles, splits A = [A_f A_s]
    (Proposition 1; Section VI for weighted blocks), forms d = 1 + diag(A_s A_s^T),
    S = I + A_f^T D^{-1} A_f (written over lower-triangle columns: W_f^{-1} + ...,
-   W_f the weights 1 / 2) and its FP64 Cholesky factor, h = M^{-1} zeta and
+   W_f the weights 1 / 2), its FP64 Cholesky factor and from it S^{-1}, h = M^{-1} zeta and
    eta = 1 + zeta^T h with zeta = (c, -b) (Section IV-B), uploads everything to the
    current HIP device, and sets the cold start u = v = (0, 0, 1).
    A, b (m), c (n), K, s: host inputs.  s may be NULL (defaults).  hip_stream: a

@@ -21,11 +21,11 @@ namespace {
 thread_local std::string g_setup_error;
 
 // dynamic LDS a solver launch may take (gfx950: 160 KiB per workgroup, minus the static part)
-const int kLdsBudget = 150 * 1024;
+const int kLdsBudget = 159 * 1024;   // of the 160 KiB per workgroup, the rest for static LDS
 // mixed form: the FP32 phase hands over after this many residual checks without a 10 % gain.
 // An FP32-stored iterate has a residual floor of about eps_32 |A| |y| / tau (above 1e-4 on the
 // Lyapunov family), so the hand-over should come soon after the floor is reached.
-const int kStallChecks = 2;
+const int kStallChecks = 4;
 
 double wall_clock_khz() {
     int dev = 0, khz = 0;
@@ -119,7 +119,7 @@ struct sos_batch {
     unsigned long long *d_ts = nullptr;   // wall-clock stamps of the solve and polish kernels
     double last_ms = 0.0, phase_ms[2] = {0.0, 0.0};
     bool use_graph = true;
-    int warm_eig = 1, lds_budget = 0, eig_wave = 1;
+    int warm_eig = 1, lds_budget = 0, eig_wave = 2;
     int gs_bucket[7] = {16, 16, 16, 16, 16, 16, 16};
     sos_settings st{};
 };
@@ -315,14 +315,32 @@ void build(sos_work *w, const sos_csc *A, const double *b, const double *c, cons
             for (int q = frptr[r]; q < frptr[r + 1]; ++q)
                 S[(size_t)frcol[p] * k + frcol[q]] += frval[p] * frval[q] * dinv[r];
     cholesky(S, k);
-    std::vector<double> Lcol, Lrow, Ldinv(k);
-    Lcol.reserve((size_t)k * (k + 1) / 2);
-    Lrow.reserve((size_t)k * (k + 1) / 2);
-    for (int j = 0; j < k; ++j)
-        for (int i = j; i < k; ++i) Lcol.push_back(S[(size_t)i * k + j]);
+    // S^{-1} = L^{-T} L^{-1}, formed once in FP64 so that each iteration's solve with S is
+    // one dense matrix-vector product: Li = L^{-1} (lower, by forward substitution on the
+    // columns of I), then Sinv[i][j] = sum_{l >= max(i,j)} Li[l][i] Li[l][j]
+    // (both loops stream rows, row-major)
+    std::vector<double> Li((size_t)k * k, 0.0), Sinv((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i) {   // row i of L^{-1}: L[i][0..i] Li[0..i][j] = delta_ij
+        double *li = &Li[(size_t)i * k];
+        for (int p = 0; p < i; ++p) {
+            const double lip = S[(size_t)i * k + p];
+            const double *lp = &Li[(size_t)p * k];
+            for (int j = 0; j <= p; ++j) li[j] -= lip * lp[j];
+        }
+        li[i] = 1.0;
+        const double dinv_i = 1.0 / S[(size_t)i * k + i];
+        for (int j = 0; j <= i; ++j) li[j] *= dinv_i;
+    }
+    for (int l = 0; l < k; ++l) {   // Sinv += row_l(Li)^T row_l(Li), lower triangle
+        const double *ll = &Li[(size_t)l * k];
+        for (int i = 0; i <= l; ++i) {
+            const double a = ll[i];
+            double *si = &Sinv[(size_t)i * k];
+            for (int j = 0; j <= i; ++j) si[j] += a * ll[j];
+        }
+    }
     for (int i = 0; i < k; ++i)
-        for (int j = 0; j <= i; ++j) Lrow.push_back(S[(size_t)i * k + j]);
-    for (int j = 0; j < k; ++j) Ldinv[j] = 1.0 / S[(size_t)j * k + j];
+        for (int j = 0; j < i; ++j) Sinv[(size_t)j * k + i] = Sinv[(size_t)i * k + j];
 
     // h = M^{-1} zeta, zeta = (c, -b): the same Woodbury route, in FP64 on the host
     std::vector<double> bv(b, b + m);
@@ -423,9 +441,7 @@ void build(sos_work *w, const sos_csc *A, const double *b, const double *c, cons
     P.frval32 = up_f(frval);
     P.dinv64 = up_d(dinv);
     P.dinv32 = up_f(dinv);
-    P.Lcol = up_d(Lcol);
-    P.Lrow = up_d(Lrow);
-    P.Ldinv = up_d(Ldinv);
+    P.Sinv = up_d(Sinv);
     P.h64 = up_d(h);
     P.h32 = up_f(h);
     P.b64 = up_d(bv);
@@ -495,7 +511,7 @@ RunParams single_params(sos_work *w, int mode, int iters, int min_iters, double 
     rp.eig_ld = w->eig_ld;
     rp.max_sweeps = 60;
     rp.warm_eig = 1;
-    rp.eig_wave = 1;
+    rp.eig_wave = 2;
     rp.lds_budget = kLdsBudget;
     for (int i = 0; i < 7; ++i) rp.gs_bucket[i] = 16;
     return rp;
@@ -833,10 +849,10 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         B->max_sweeps = (int)json_num(schedule_json, "max_sweeps", 60);
         B->use_graph = json_num(schedule_json, "use_graph", 1) != 0.0;
         B->warm_eig = (int)json_num(schedule_json, "warm_eig", 1);
-        B->eig_wave = (int)json_num(schedule_json, "eig_wave", 1);
+        B->eig_wave = (int)json_num(schedule_json, "eig_wave", 2);
         // LDS per workgroup: what wg_per_cu resident workgroups can share (160 KiB per CU, less
         // about 10 KiB of static LDS each), unless the schedule says otherwise
-        const double lds_share = std::min<double>(kLdsBudget, 163840.0 / B->wg_per_cu - 10240.0);
+        const double lds_share = std::min<double>(kLdsBudget, 163840.0 / B->wg_per_cu - 1024.0);
         B->lds_budget = (int)(json_num(schedule_json, "lds_kb", lds_share / 1024.0) * 1024.0);
         if (B->lds_budget < 0 || B->lds_budget > kLdsBudget) throw Status(SOS_E_INVAL, "schedule lds_kb out of range");
         static const char *gs_keys[7] = {"gs_n32", "gs_n64", "gs_n96", "gs_n128", "gs_n192", "gs_n256", "gs_big"};

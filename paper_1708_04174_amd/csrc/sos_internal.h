@@ -37,9 +37,9 @@ struct ProbDesc {
     const double *frval64; const float *frval32;
     // 1/d, d = 1 + diag(A_s A_s^T)
     const double *dinv64; const float *dinv32;
-    // Cholesky factor of S = W_f^{-1} + A_f^T D^{-1} A_f (W_f = wgt on the A_f columns),
-    // packed lower, by columns and by rows
-    const double *Lcol, *Lrow, *Ldinv;
+    // S^{-1}, S = W_f^{-1} + A_f^T D^{-1} A_f (W_f = wgt on the A_f columns): k x k,
+    // symmetric, formed in FP64 from the Cholesky factor of S at setup
+    const double *Sinv;
     // h = M^{-1} zeta (nx + m), b (m), c (nx), cw = wgt * c (nx), wgt (nx)
     const double *h64; const float *h32;
     const double *b64; const float *b32;
@@ -82,7 +82,7 @@ struct RunParams {
     int max_sweeps;
     int warm_eig;           // start each block's Jacobi sweeps from the previous iteration's eigenvectors
     int lds_budget;         // dynamic LDS bytes the launch may use
-    int eig_wave;           // 1: blocks that fit in LDS use the one-wavefront eigensolver
+    int eig_wave;           // blocks that fit in LDS: 1 one-wavefront eigensolver, 2 rows split over wavefronts
     int lds_mat_off, lds_nmax, lds_nmax_g, lpj_nmax;   // filled in by the launcher
     int accumulate;         // 0: out[TOTAL] = iterations of this launch; 1: out[TOTAL] += them, and the
                             //    iteration budget is iters - out[TOTAL] (at least min_iters)

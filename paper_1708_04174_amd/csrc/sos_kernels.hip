@@ -117,28 +117,29 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// z <- (L L^T)^{-1} z in FP64 by one wavefront; z lives in LDS (k entries).
-// Forward substitution by columns of L, backward by rows of L (= columns of L^T).
-__device__ void chol_solve_wave(const double *__restrict__ Lcol, const double *__restrict__ Lrow,
-                                const double *__restrict__ Ldinv, int k, double *z) {
-    const int lane = threadIdx.x & 63;
-    long long cs = 0;   // start of column j in the column-packed factor
-    for (int j = 0; j < k; ++j) {
-        const double yj = z[j] * Ldinv[j];
-        const double *col = Lcol + cs;   // L[j..k-1][j]
-        for (int i = j + 1 + lane; i < k; i += 64) z[i] -= col[i - j] * yj;
-        wave_sync_lds();
-        if (lane == 0) z[j] = yj;
-        wave_sync_lds();
-        cs += k - j;
+// z <- S^{-1} z in FP64 by the workgroup; z (k entries) and part (NT entries) in LDS.
+// Each row's sum is split into nseg contiguous segments of the column range, one thread
+// per (row, segment); reads of S^{-1} by column are coalesced across threads (S^{-1} is
+// symmetric, so column i read down is row i).  Segment sums are added in a fixed order.
+template <int NT>
+__device__ __forceinline__ void schur_solve(const double *__restrict__ Sinv, int k, double *z, double *part) {
+    const int tid = threadIdx.x;
+    const int kp = (k + 63) & ~63;
+    const int nseg = kp >= NT ? 1 : NT / kp;
+    for (int t = tid; t < kp * nseg; t += NT) {
+        const int i = t % kp, sg = t / kp;
+        double acc = 0.0;
+        if (i < k) {
+            const int j0 = sg * k / nseg, j1 = (sg + 1) * k / nseg;
+            for (int j = j0; j < j1; ++j) acc += Sinv[(long long)j * k + i] * z[j];
+        }
+        part[t] = acc;   // t < kp nseg <= max(kp, NT) <= 1024
     }
-    for (int i = k - 1; i >= 0; --i) {
-        const double xi = z[i] * Ldinv[i];
-        const double *row = Lrow + (long long)i * (i + 1) / 2;   // L[i][0..i]
-        for (int j = lane; j < i; j += 64) z[j] -= row[j] * xi;
-        wave_sync_lds();
-        if (lane == 0) z[i] = xi;
-        wave_sync_lds();
+    __syncthreads();
+    for (int i = tid; i < k; i += NT) {
+        double s = 0.0;
+        for (int sg = 0; sg < nseg; ++sg) s += part[sg * kp + i];
+        z[i] = s;
     }
 }
 
@@ -195,7 +196,7 @@ __device__ __noinline__ void affine_phase(const ProbDesc &P, const RunParams &rp
             if (lane == 0) s_z[j] = s;
         }
         __syncthreads();
-        if (wid == 0) chol_solve_wave(P.Lcol, P.Lrow, P.Ldinv, k, s_z);
+        schur_solve<NT>(P.Sinv, k, s_z, s_z + SOS_KMAX_LDS);
         __syncthreads();
     }
 
@@ -321,12 +322,57 @@ __device__ __forceinline__ float wave_allsum(float x) {
     return __shfl(x, 0, 64);
 }
 
+// Wave maximum, lane 0's result broadcast (uniform across the wave).
+template <typename T>
+__device__ __forceinline__ T wave_allmax(T x) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const T y = __shfl_down(x, off, 64);
+        x = y > x ? y : x;
+    }
+    return __shfl(x, 0, 64);
+}
+
 // Sum over a group of GS consecutive lanes; every lane of the group gets the group's first
 // lane's result, so branches on it are uniform inside the group.
 template <int GS, typename T>
 __device__ __forceinline__ T group_allsum(T x) {
     for (int off = GS / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, GS);
     return __shfl(x, 0, GS);
+}
+
+// Jacobi rotation for the column pair with squared norms al, be and inner product ga:
+// rotate only while the pair is coupled beyond rounding, relative to both columns
+// (ga^2 > tol2 al be) and absolutely (ga^2 > atol2 max(al, be)); then t = tan(theta) of the
+// smaller of the two angles that make the pair orthogonal, t = 2 ga sgn(d) / (|d| + hypot(d, 2 ga))
+// with d = be - al, c = 1 / sqrt(1 + t^2), s = c t.  FP32 uses the native reciprocal and
+// root instructions (1 ulp; c^2 + s^2 = 1 to that level), FP64 the IEEE operations.
+template <typename T>
+__device__ __forceinline__ bool jacobi_rot(T al, T be, T ga, T tol2, T atol2, T &c, T &s);
+template <>
+__device__ __forceinline__ bool jacobi_rot<float>(float al, float be, float ga, float tol2, float atol2, float &c,
+                                                  float &s) {
+    const float g2 = ga * ga;
+    if (!(g2 > tol2 * (al * be)) || !(g2 > atol2 * (al > be ? al : be))) return false;
+    const float d = be - al;
+    const float h = __builtin_amdgcn_sqrtf(d * d + 4.0f * g2);
+    float t = 2.0f * ga * __builtin_amdgcn_rcpf(fabsf(d) + h);
+    if (d < 0.0f) t = -t;
+    c = __builtin_amdgcn_rsqf(1.0f + t * t);
+    s = c * t;
+    return true;
+}
+template <>
+__device__ __forceinline__ bool jacobi_rot<double>(double al, double be, double ga, double tol2, double atol2,
+                                                   double &c, double &s) {
+    const double g2 = ga * ga;
+    if (!(g2 > tol2 * (al * be)) || !(g2 > atol2 * (al > be ? al : be))) return false;
+    const double d = be - al;
+    const double h = sqrt(d * d + 4.0 * g2);
+    double t = 2.0 * ga / (fabs(d) + h);
+    if (d < 0.0) t = -t;
+    c = 1.0 / sqrt(1.0 + t * t);
+    s = c * t;
+    return true;
 }
 
 // One-sided Jacobi rotation of the column pair (p, q) of G (and of V) by a group of GS
@@ -355,10 +401,8 @@ __device__ __forceinline__ bool os_rotate_pair(GP G, int ldg, VP V, int ldv, int
         al = group_allsum<GS>(al);
         be = group_allsum<GS>(be);
         ga = group_allsum<GS>(ga);
-        if (!(fabs(ga) > tol * sqrt(al * be)) || !(fabs(ga) > atol * sqrt(al > be ? al : be))) return false;
-        const T ze = (be - al) / ((T)2 * ga);
-        const T tt = (ze >= (T)0 ? (T)1 : (T)-1) / (fabs(ze) + sqrt((T)1 + ze * ze));
-        const T cc = (T)1 / sqrt((T)1 + tt * tt), ss = cc * tt;
+        T cc, ss;
+        if (!jacobi_rot<T>(al, be, ga, tol * tol, atol * atol, cc, ss)) return false;
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
             const int i = gl + GS * t;
@@ -381,10 +425,8 @@ __device__ __forceinline__ bool os_rotate_pair(GP G, int ldg, VP V, int ldv, int
     al = group_allsum<GS>(al);
     be = group_allsum<GS>(be);
     ga = group_allsum<GS>(ga);
-    if (!(fabs(ga) > tol * sqrt(al * be)) || !(fabs(ga) > atol * sqrt(al > be ? al : be))) return false;
-    const T ze = (be - al) / ((T)2 * ga);
-    const T tt = (ze >= (T)0 ? (T)1 : (T)-1) / (fabs(ze) + sqrt((T)1 + ze * ze));
-    const T cc = (T)1 / sqrt((T)1 + tt * tt), ss = cc * tt;
+    T cc, ss;
+    if (!jacobi_rot<T>(al, be, ga, tol * tol, atol * atol, cc, ss)) return false;
     for (int i = gl; i < N; i += GS) {
         const T a = gp[i], b = gq[i];
         gp[i] = cc * a - ss * b;
@@ -449,6 +491,7 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+#pragma unroll 4
             for (int kk = 0; kk < N; ++kk) {
                 T wa[4], vb[4];
 #pragma unroll
@@ -579,12 +622,37 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
 
 // ----------------------------------------------------------------------------- PSD projection, one wavefront
 // Leading dimension for a column-major N x N matrix in LDS that one wavefront walks lane
-// per column: ld = 1 (mod 32 banks), so lanes reading element i of distinct columns hit
-// distinct banks.
-__host__ __device__ __forceinline__ int lpj_ld(int N, int elem_bytes) {
-    const int q = elem_bytes == 4 ? 32 : 16;
-    return q * ((N - 1 + q - 1) / q) + 1;
+// per column with 16-byte reads: rows are padded with zeros to a whole number of 32-byte
+// chunks (kLpjChunk elements) and ld = 4 dwords (mod 32 banks), so lanes reading the same
+// chunk of columns p and p' with p != p' (mod 8) hit distinct 4-bank groups.
+__host__ __device__ __forceinline__ int lpj_rows(int N, int elem_bytes) {
+    const int c = 32 / elem_bytes;
+    return (N + c - 1) / c * c;
 }
+__host__ __device__ __forceinline__ int lpj_ld(int N, int elem_bytes) {
+    const int q = 128 / elem_bytes, r = 16 / elem_bytes;
+    const int np = lpj_rows(N, elem_bytes);
+    return q * ((np - r + q - 1) / q) + r;
+}
+
+// LDS footprint (elements) of one block in the one-wavefront solver: G, V, then sigma
+__host__ __device__ __forceinline__ int lpj_region(int N, int elem_bytes) {
+    return 2 * N * lpj_ld(N, elem_bytes) + ((N + 3) & ~3);
+}
+
+// 16-byte vector of T, in LDS
+template <typename T> struct V16;
+template <> struct V16<float> {
+    typedef float v __attribute__((ext_vector_type(4)));
+    static constexpr int n = 4;
+};
+template <> struct V16<double> {
+    typedef double v __attribute__((ext_vector_type(2)));
+    static constexpr int n = 2;
+};
+template <typename T> __device__ __forceinline__ T hsum(typename V16<T>::v x);
+template <> __device__ __forceinline__ float hsum<float>(V16<float>::v x) { return (x.x + x.y) + (x.z + x.w); }
+template <> __device__ __forceinline__ double hsum<double>(V16<double>::v x) { return x.x + x.y; }
 
 __device__ __forceinline__ void wave_fence_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -628,6 +696,12 @@ __device__ __noinline__ void project_block_wave(T *__restrict__ vs, T *__restric
             V[j * ld + i] = (i == j) ? (T)1 : (T)0;
         }
     }
+    const int Np = lpj_rows(N, (int)sizeof(T));
+    for (int idx = lane; idx < (Np - N) * N; idx += 64) {
+        const int j = idx / (Np - N), i = N + idx - (idx / (Np - N)) * (Np - N);
+        G[j * ld + i] = (T)0;
+        V[j * ld + i] = (T)0;
+    }
     fro2 = wave_allsum(fro2);
     wave_fence_sync();
     if (warm) {
@@ -640,6 +714,7 @@ __device__ __noinline__ void project_block_wave(T *__restrict__ vs, T *__restric
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+#pragma unroll 4
             for (int kk = 0; kk < N; ++kk) {
                 T wa[4], vb[4];
 #pragma unroll
@@ -659,49 +734,88 @@ __device__ __noinline__ void project_block_wave(T *__restrict__ vs, T *__restric
         }
         wave_fence_sync();
     }
+    typedef typename V16<T>::v VT;
+    typedef __attribute__((address_space(3))) VT LVT;
+    const int nv = Np / V16<T>::n;   // 16-byte vectors per column, even
     const T tol = (T)(16.0 * TS<T>::eps);
     const T atol = (T)(TS<T>::eps * sqrt(fro2));
+    const T tol2 = tol * tol, atol2 = atol * atol;
     const int M = N + (N & 1);
     const int H = M / 2;
     int nsw = 0;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         int rotated = 0;
+        T mr = (T)0;   // largest squared relative coupling ga^2 / (al be) rotated away in this sweep
         for (int r = 0; r < M - 1; ++r) {
             for (int kk = lane; kk < H; kk += 64) {
+                // round-robin pair without ordering p < q (the rotation does not need it):
+                // lanes kk, kk+1, ... then touch consecutive columns r+kk and r-kk, whose
+                // 16-byte chunks fall in distinct bank groups
                 int p, q;
-                rr_pair(r, kk, M, p, q);
-                if (q >= N) continue;
-                LT *gp = G + p * ld, *gq = G + q * ld;
-                T al = 0, be = 0, ga = 0;
-#pragma unroll 4
-                for (int i = 0; i < N; ++i) {
-                    const T a = gp[i], b = gq[i];
-                    al += a * a;
-                    be += b * b;
-                    ga += a * b;
+                if (kk == 0) {
+                    p = r;
+                    q = M - 1;
+                } else {
+                    p = r + kk;
+                    if (p >= M - 1) p -= M - 1;
+                    q = r - kk;
+                    if (q < 0) q += M - 1;
                 }
-                if (!(fabs(ga) > tol * sqrt(al * be)) || !(fabs(ga) > atol * sqrt(al > be ? al : be))) continue;
-                const T ze = (be - al) / ((T)2 * ga);
-                const T tt = (ze >= (T)0 ? (T)1 : (T)-1) / (fabs(ze) + sqrt((T)1 + ze * ze));
-                const T cc = (T)1 / sqrt((T)1 + tt * tt), ss = cc * tt;
-                LT *vp = V + p * ld, *vq = V + q * ld;
-#pragma unroll 4
-                for (int i = 0; i < N; ++i) {
-                    const T a = gp[i], b = gq[i];
-                    gp[i] = cc * a - ss * b;
-                    gq[i] = ss * a + cc * b;
-                    const T c = vp[i], d = vq[i];
-                    vp[i] = cc * c - ss * d;
-                    vq[i] = ss * c + cc * d;
+                if (p >= N || q >= N) continue;
+                // columns p, q of G and V in 32-byte chunks (two 16-byte vectors per column);
+                // rows N..Np-1 are zero, so whole chunks need no tail
+                LVT *gp = (LVT *)(G + p * ld), *gq = (LVT *)(G + q * ld);
+                VT sa = (VT)(T)0, sb = (VT)(T)0, sg = (VT)(T)0;
+#pragma unroll 2
+                for (int c = 0; c < nv; c += 2) {
+                    const VT a0 = gp[c], a1 = gp[c + 1], b0 = gq[c], b1 = gq[c + 1];
+                    sa += a0 * a0 + a1 * a1;
+                    sb += b0 * b0 + b1 * b1;
+                    sg += a0 * b0 + a1 * b1;
+                }
+                const T al = hsum<T>(sa), be = hsum<T>(sb), ga = hsum<T>(sg);
+                T cc, ss;
+                if (!jacobi_rot<T>(al, be, ga, tol2, atol2, cc, ss)) continue;
+                {
+                    const T r2 = ga * ga / (al * be);
+                    mr = r2 > mr ? r2 : mr;
+                }
+                LVT *vp = (LVT *)(V + p * ld), *vq = (LVT *)(V + q * ld);
+                // software pipelined: the next chunk is read before the current one is written
+                // (columns p and q are distinct, so the two never overlap)
+                VT A0 = gp[0], A1 = gp[1], B0 = gq[0], B1 = gq[1];
+                VT C0 = vp[0], C1 = vp[1], D0 = vq[0], D1 = vq[1];
+                for (int c = 0; c < nv; c += 2) {
+                    VT nA0, nA1, nB0, nB1, nC0, nC1, nD0, nD1;
+                    const bool more = c + 2 < nv;
+                    if (more) {
+                        nA0 = gp[c + 2]; nA1 = gp[c + 3]; nB0 = gq[c + 2]; nB1 = gq[c + 3];
+                        nC0 = vp[c + 2]; nC1 = vp[c + 3]; nD0 = vq[c + 2]; nD1 = vq[c + 3];
+                    }
+                    gp[c] = cc * A0 - ss * B0;
+                    gp[c + 1] = cc * A1 - ss * B1;
+                    gq[c] = ss * A0 + cc * B0;
+                    gq[c + 1] = ss * A1 + cc * B1;
+                    vp[c] = cc * C0 - ss * D0;
+                    vp[c + 1] = cc * C1 - ss * D1;
+                    vq[c] = ss * C0 + cc * D0;
+                    vq[c + 1] = ss * C1 + cc * D1;
+                    if (more) {
+                        A0 = nA0; A1 = nA1; B0 = nB0; B1 = nB1;
+                        C0 = nC0; C1 = nC1; D0 = nD0; D1 = nD1;
+                    }
                 }
                 rotated = 1;
             }
             wave_fence_sync();
         }
         ++nsw;
-        if (!__any(rotated)) break;
+        // converged: no rotation, or every rotation of the sweep was small (relative
+        // coupling <= sqrt(tol)); cyclic Jacobi converges quadratically, so what such a
+        // sweep leaves is coupling of order tol, which the next sweep would not rotate
+        if (!__any(rotated) || wave_allmax(mr) <= tol) break;
     }
-    if (lane == 0) *sweeps += nsw;
+    if (lane == 0) atomicAdd(sweeps, nsw);
     for (int j = lane; j < N; j += 64) {
         T s = 0;
         const LT *gj = G + j * ld;
@@ -758,6 +872,279 @@ __device__ __noinline__ void project_block_wave(T *__restrict__ vs, T *__restric
     wave_fence_sync();
 }
 
+// ----------------------------------------------------------------------------- PSD projection, rows per wavefront
+// Same projection again, with the rows of the column-major N x N matrices G and V split
+// over the NW wavefronts of the workgroup: wavefront w owns rows [w R, (w + 1) R) of every
+// column (R a multiple of the 16-byte vector width; rows N..NW R - 1 are zero).  Lane kk
+// of every wavefront takes column pair kk of the round: each wavefront forms partial inner
+// products over its rows, the partials meet in LDS (one workgroup barrier per round),
+// every wavefront sums them in the same order, so all take bitwise-equal rotation
+// decisions, and each rotates its own rows.  No wavefront touches another's rows of G or
+// V; the barrier only guards the partials, which alternate between two buffers by round
+// parity (a wavefront can only be one round ahead of the slowest).
+__host__ __device__ __forceinline__ int rows_R(int N, int elem_bytes, int nw) {
+    const int vw = 16 / elem_bytes;
+    const int r = (N + nw - 1) / nw;
+    return (r + vw - 1) / vw * vw;
+}
+// leading dimension: at least NW R, and 16 bytes (mod 128): lanes on consecutive columns
+// read distinct 4-bank groups
+__host__ __device__ __forceinline__ int rows_ld(int N, int elem_bytes, int nw) {
+    const int q = 128 / elem_bytes, r = 16 / elem_bytes;
+    const int np = nw * rows_R(N, elem_bytes, nw);
+    return q * ((np - r + q - 1) / q) + r;
+}
+// column pairs per round, rounded up to 16
+__host__ __device__ __forceinline__ int rows_hp(int N) {
+    const int H = (N + (N & 1)) / 2;
+    return (H + 15) / 16 * 16;
+}
+// LDS elements of one block: G, V, two buffers of 3 x nw x hp partial sums, sigma
+__host__ __device__ __forceinline__ long long rows_region(int N, int elem_bytes, int nw) {
+    return 2LL * N * rows_ld(N, elem_bytes, nw) + 2LL * 3 * nw * rows_hp(N) + ((N + 3) & ~3);
+}
+
+template <typename T, int NT>
+__device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restrict__ us, int N, T *__restrict__ Vs,
+                                                bool warm, typename Lds<T>::type *G, T *__restrict__ Tm,
+                                                const EigScratch &sc, int max_sweeps) {
+    typedef typename Lds<T>::type LT;
+    typedef typename V16<T>::v VT;
+    typedef __attribute__((address_space(3))) VT LVT;
+    constexpr int NW = NT / 64;
+    constexpr int VW = V16<T>::n;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (N == 1) {
+        if (tid == 0) {
+            const T x0 = vs[0];
+            const T x = x0 > (T)0 ? x0 : (T)0;
+            us[0] = x;
+            vs[0] = x - x0;
+            if (Vs) Vs[0] = (T)1;
+        }
+        __syncthreads();
+        return;
+    }
+    const int R = rows_R(N, (int)sizeof(T), NW);
+    const int ld = rows_ld(N, (int)sizeof(T), NW);
+    const int HP = rows_hp(N);
+    const int Np = NW * R;
+    LT *V = G + (long long)N * ld;
+    LT *part = V + (long long)N * ld;   // [2][3][NW][HP]
+    LT *sig = part + 2 * 3 * NW * HP;
+    double fro2 = 0.0, dummy = 0.0;
+    for (int idx = tid; idx < N * N; idx += NT) {
+        const int j = idx / N, i = idx - (idx / N) * N;
+        const int a = i > j ? i : j, bb = i > j ? j : i;
+        const T x = vs[svec_idx(a, bb, N)];
+        fro2 += (double)x * (double)x;
+        if (warm) {
+            Tm[j * N + i] = x;
+            V[j * ld + i] = Vs[j * N + i];
+        } else {
+            G[j * ld + i] = x;
+            V[j * ld + i] = (i == j) ? (T)1 : (T)0;
+        }
+    }
+    for (int idx = tid; idx < (Np - N) * N; idx += NT) {
+        const int j = idx / (Np - N), i = N + idx - (idx / (Np - N)) * (Np - N);
+        G[j * ld + i] = (T)0;
+        V[j * ld + i] = (T)0;
+    }
+    block_sum2<NT>(fro2, dummy, sc.s_red);   // its barriers also publish G, V, Tm
+    if (warm) {
+        // G = W V_prev, 4 x 4 tiles over the workgroup
+        const int nt = (N + 3) >> 2;
+        for (int t = tid; t < nt * nt; t += NT) {
+            const int i0 = (t / nt) * 4, j0 = (t - (t / nt) * nt) * 4;
+            T acc[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+#pragma unroll 4
+            for (int kk = 0; kk < N; ++kk) {
+                T wa[4], vb[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) wa[a] = (i0 + a < N) ? Tm[kk * N + i0 + a] : (T)0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) vb[b] = (j0 + b < N) ? V[(j0 + b) * ld + kk] : (T)0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] += wa[a] * vb[b];
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (i0 + a < N && j0 + b < N) G[(j0 + b) * ld + i0 + a] = acc[a][b];
+        }
+        __syncthreads();
+    }
+    const T tol = (T)(16.0 * TS<T>::eps);
+    const T atol = (T)(TS<T>::eps * sqrt(fro2));
+    const T tol2 = tol * tol, atol2 = atol * atol;
+    const int M = N + (N & 1);
+    const int H = M / 2;
+    const int nvw = R / VW;              // vectors per column in this wavefront's rows
+    const int row0 = w * R;
+    int nsw = 0, round = 0;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        int rotated = 0;
+        T mr = (T)0;   // largest squared relative coupling ga^2 / (al be) rotated away in this sweep
+        for (int r = 0; r < M - 1; ++r, ++round) {
+            LT *pb = part + (round & 1) * 3 * NW * HP;
+            // partial inner products over this wavefront's rows
+            for (int kk = lane; kk < H; kk += 64) {
+                int p, q;
+                if (kk == 0) {
+                    p = r;
+                    q = M - 1;
+                } else {
+                    p = r + kk;
+                    if (p >= M - 1) p -= M - 1;
+                    q = r - kk;
+                    if (q < 0) q += M - 1;
+                }
+                T al = 0, be = 0, ga = 0;
+                if (p < N && q < N) {
+                    const LVT *gp = (const LVT *)(G + p * ld + row0), *gq = (const LVT *)(G + q * ld + row0);
+                    VT sa = (VT)(T)0, sb = (VT)(T)0, sg = (VT)(T)0;
+#pragma unroll 2
+                    for (int c = 0; c < nvw; ++c) {
+                        const VT a = gp[c], b = gq[c];
+                        sa += a * a;
+                        sb += b * b;
+                        sg += a * b;
+                    }
+                    al = hsum<T>(sa);
+                    be = hsum<T>(sb);
+                    ga = hsum<T>(sg);
+                }
+                pb[(0 * NW + w) * HP + kk] = al;
+                pb[(1 * NW + w) * HP + kk] = be;
+                pb[(2 * NW + w) * HP + kk] = ga;
+            }
+            __syncthreads();
+            for (int kk = lane; kk < H; kk += 64) {
+                int p, q;
+                if (kk == 0) {
+                    p = r;
+                    q = M - 1;
+                } else {
+                    p = r + kk;
+                    if (p >= M - 1) p -= M - 1;
+                    q = r - kk;
+                    if (q < 0) q += M - 1;
+                }
+                if (p >= N || q >= N) continue;
+                T al = 0, be = 0, ga = 0;
+#pragma unroll
+                for (int x = 0; x < NW; ++x) {
+                    al += pb[(0 * NW + x) * HP + kk];
+                    be += pb[(1 * NW + x) * HP + kk];
+                    ga += pb[(2 * NW + x) * HP + kk];
+                }
+                T cc, ss;
+                if (!jacobi_rot<T>(al, be, ga, tol2, atol2, cc, ss)) continue;
+                {
+                    const T r2 = ga * ga / (al * be);
+                    mr = r2 > mr ? r2 : mr;
+                }
+                LVT *gp = (LVT *)(G + p * ld + row0), *gq = (LVT *)(G + q * ld + row0);
+                LVT *vp = (LVT *)(V + p * ld + row0), *vq = (LVT *)(V + q * ld + row0);
+                // one 16-byte vector per column at a time, the next one read before the
+                // current one is written (columns p and q are distinct, so they never overlap)
+                VT A = gp[0], Bv = gq[0], C = vp[0], D = vq[0];
+                for (int c = 0; c < nvw; ++c) {
+                    VT nA, nB, nC, nD;
+                    const bool more = c + 1 < nvw;
+                    if (more) {
+                        nA = gp[c + 1];
+                        nB = gq[c + 1];
+                        nC = vp[c + 1];
+                        nD = vq[c + 1];
+                    }
+                    gp[c] = cc * A - ss * Bv;
+                    gq[c] = ss * A + cc * Bv;
+                    vp[c] = cc * C - ss * D;
+                    vq[c] = ss * C + cc * D;
+                    if (more) {
+                        A = nA;
+                        Bv = nB;
+                        C = nC;
+                        D = nD;
+                    }
+                }
+                rotated = 1;
+            }
+            // this wavefront's next partials read rows its own lanes just rotated
+            wave_fence_sync();
+        }
+        ++nsw;
+        // every wavefront took the same decisions, so the vote needs no exchange; converged
+        // as in the one-wavefront form (no rotation, or all rotations of the sweep small)
+        if (!__any(rotated) || wave_allmax(mr) <= tol) break;
+    }
+    if (tid == 0) *sc.s_sweeps += nsw;
+    __syncthreads();
+    for (int j = tid; j < N; j += NT) {
+        const LVT *gj = (const LVT *)(G + j * ld);
+        VT s = (VT)(T)0;
+        for (int c = 0; c < Np / VW; ++c) s += gj[c] * gj[c];
+        sig[j] = sqrt(hsum<T>(s));
+    }
+    __syncthreads();
+    // u = lower((W + V Sigma V^T) / 2), v = u - w, 4 x 4 tiles on and below the diagonal
+    const int nt = (N + 3) >> 2;
+    const int ntri = nt * (nt + 1) / 2;
+    for (int t = tid; t < ntri; t += NT) {
+        int ta = 0, rem = t;
+        while (rem > ta) {
+            rem -= ta + 1;
+            ++ta;
+        }
+        const int a0 = ta * 4, b0 = rem * 4;
+        T acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+        for (int j = 0; j < N; ++j) {
+            const T sg = sig[j];
+            T va[4], vb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) va[a] = (a0 + a < N) ? V[j * ld + a0 + a] * sg : (T)0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) vb[b] = (b0 + b < N) ? V[j * ld + b0 + b] : (T)0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] += va[a] * vb[b];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = a0 + a, j = b0 + b;
+                if (i < N && j <= i) {
+                    const int s = svec_idx(i, j, N);
+                    const T x0 = vs[s];
+                    const T x = (T)0.5 * (x0 + acc[a][b]);
+                    us[s] = x;
+                    vs[s] = x - x0;
+                }
+            }
+    }
+    if (Vs)
+        for (int idx = tid; idx < N * N; idx += NT) {
+            const int j = idx / N, i = idx - (idx / N) * N;
+            Vs[j * N + i] = V[j * ld + i];
+        }
+    __syncthreads();
+}
+
 // ----------------------------------------------------------------------------- residuals (FP64)
 template <typename T, int NT>
 __device__ __noinline__ int residual_phase(const ProbDesc &P, double tol, double *s_red, int iters_done, double *res_max = nullptr) {
@@ -809,7 +1196,15 @@ __device__ __noinline__ int residual_phase(const ProbDesc &P, double tol, double
         dobj = by / tau;
     }
     const double mx = fmax(rpn, fmax(rdn, gap));
-    if (res_max) *res_max = mx;
+    if (res_max) {
+        // progress measures: the largest residual, and (once tau has collapsed) the smaller
+        // relative error of the two infeasibility certificates
+        double ce = INFINITY;
+        if (by > 0.0) ce = fmin(ce, sqrt(saty) / by);
+        if (cx < 0.0) ce = fmin(ce, sqrt(sax) / (-cx));
+        res_max[0] = mx;
+        res_max[1] = ce;
+    }
     if (mx <= tol) status = 1;
     else if (by > 0.0 && sqrt(saty) <= tol * by) status = 2;
     else if (cx < 0.0 && sqrt(sax) <= tol * (-cx)) status = 3;
@@ -841,12 +1236,14 @@ __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
     __shared__ int s_flag;
     __shared__ int s_sweeps;
     __shared__ double s_red[4 * (NT / 64)];
-    __shared__ double s_z[SOS_KMAX_LDS];
-    extern __shared__ char dyn_lds[];
+    extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
     // dynamic LDS: sigma (eig_ld values), then G and V of blocks with N <= rp.lds_nmax,
     // or G alone for blocks with N <= rp.lds_nmax_g
     typename Lds<T>::type *s_sig = as_lds<T>(dyn_lds);
     typename Lds<T>::type *s_mat = as_lds<T>(dyn_lds + rp.lds_mat_off);
+    // the affine step's k-vector and the Schur solve's partial sums share the eigen
+    // region: the two phases are separated by barriers
+    double *s_z = reinterpret_cast<double *>(dyn_lds + rp.lds_mat_off);
 
     char *wbase = reinterpret_cast<char *>(rp.work) + (long long)blockIdx.x * rp.work_stride;
     char *ebase = reinterpret_cast<char *>(rp.eig) + (long long)blockIdx.x * rp.eig_stride;
@@ -882,19 +1279,67 @@ __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
             cap = rp.iters - (int)P.out[SOS_OUT_TOTAL];
             if (cap < rp.min_iters) cap = rp.min_iters;
         }
-        double best = INFINITY;
+        double best = INFINITY, best_ce = INFINITY;
+        bool was_cert = false;
         int since_best = 0;
         bool stalled = false;
+        // blocks small enough for the one-wavefront solver run side by side, one wavefront
+        // each, when there are two or three of them and their G, V, sigma fit in LDS together
+        int nl = 0;
+        long long lbytes = 0;
+        for (int bk = 0; bk < P.nblk; ++bk)
+            if (P.blk_N[bk] <= rp.lpj_nmax) {
+                ++nl;
+                lbytes += (long long)lpj_region(P.blk_N[bk], (int)sizeof(T)) * (long long)sizeof(T);
+            }
+        const bool side = rp.eig_wave == 1 && nl >= 2 && nl <= 3 && nl <= NT / 64 &&
+                          rp.lds_mat_off + lbytes <= rp.lds_budget;
         while (it < cap) {
             t0 = wall_clock64();
             affine_phase<T, NT, T>(P, rp, wy, wx, s_z, s_red);
             const unsigned long long t1 = wall_clock64();
             t_aff += t1 - t0;
+            if (side) {
+                // one wavefront per block, each with its own G, V, sigma in LDS and its own
+                // slice of the global temporary
+                const int w = threadIdx.x >> 6;
+                int li = 0;
+                long long loff = 0, vo = 0;
+                for (int bk = 0; bk < P.nblk; ++bk) {
+                    const int N = P.blk_N[bk];
+                    if (N <= rp.lpj_nmax) {
+                        if (w == li) {
+                            const int off = P.blk_off[bk];
+                            const int ldp = lpj_ld(N, (int)sizeof(T));
+                            typename Lds<T>::type *G = s_mat + loff;
+                            project_block_wave<T>(v + off, u + off, N, rp.warm_eig ? vstore + vo : nullptr,
+                                                  rp.warm_eig && warm, G, G + (long long)N * ldp, ldp,
+                                                  Tm + (long long)li * P.nmax * P.nmax, G + 2LL * N * ldp, &s_sweeps,
+                                                  rp.max_sweeps);
+                        }
+                        ++li;
+                        loff += lpj_region(N, (int)sizeof(T));
+                    }
+                    vo += (long long)N * N;
+                }
+                __syncthreads();
+            }
             long long voff = 0;
             for (int bk = 0; bk < P.nblk; ++bk) {
                 const int off = P.blk_off[bk];
                 const int N = P.blk_N[bk];
                 if (N <= rp.lpj_nmax) {
+                    if (side) {
+                        voff += (long long)N * N;
+                        continue;
+                    }
+                    if (rp.eig_wave == 2) {
+                        // rows split over the wavefronts, G, V and partial sums in LDS
+                        project_block_rows<T, NT>(v + off, u + off, N, rp.warm_eig ? vstore + voff : nullptr,
+                                                  rp.warm_eig && warm, s_mat, Tm, sc, rp.max_sweeps);
+                        voff += (long long)N * N;
+                        continue;
+                    }
                     // one wavefront, lane per column pair, G and V in LDS
                     if ((threadIdx.x >> 6) == 0) {
                         const int ldp = lpj_ld(N, (int)sizeof(T));
@@ -924,18 +1369,34 @@ __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
             ++it;
             const unsigned long long t2 = wall_clock64();
             t_eig += t2 - t1;
-            if (rp.mode == RUN_SOLVE && it >= rp.min_iters && (it % rp.check_every == 0 || it == cap)) {
-                double mx = INFINITY;
-                status = residual_phase<T, NT>(P, rp.tol, s_red, it, &mx);
+            if (rp.mode == RUN_SOLVE && it >= rp.min_iters &&
+                (it % rp.check_every == 0 || it == cap || it == rp.min_iters)) {
+                double pm[2] = {INFINITY, INFINITY};
+                status = residual_phase<T, NT>(P, rp.tol, s_red, it, pm);
                 t_res += wall_clock64() - t2;
                 if (status) break;
                 // a phase that stops improving hands over (the FP32 phase of the mixed form):
-                // stalled once stall_checks checks in a row missed 0.9 x the best residual
+                // stalled once stall_checks checks in a row (three times as many while
+                // tau = 0) missed 0.99 x the best value of the measure of the current
+                // regime: the largest residual while tau > 0, the certificate error while
+                // tau = 0 (each best kept per regime; a change of regime restarts the count)
                 if (rp.stall_checks > 0) {
-                    if (mx < 0.9 * best) {
-                        best = mx;
+                    const bool cert = !isfinite(pm[0]);
+                    bool better;
+                    if (!cert) {
+                        better = pm[0] < 0.99 * best;
+                        best = fmin(best, pm[0]);
+                    } else {
+                        better = !isfinite(pm[1]) || pm[1] < 0.99 * best_ce;
+                        best_ce = fmin(best_ce, pm[1]);
+                    }
+                    if (cert != was_cert) better = true;
+                    was_cert = cert;
+                    // the certificate error decays like 1/k with bumps, and the FP32
+                    // iterate carries it down to about 5 tol: a longer window there
+                    if (better) {
                         since_best = 0;
-                    } else if (++since_best >= rp.stall_checks) {
+                    } else if (++since_best >= (cert ? 3 * rp.stall_checks : rp.stall_checks)) {
                         stalled = true;
                         break;
                     }
@@ -969,7 +1430,7 @@ __global__ __launch_bounds__(NT) void warm_start_kernel(RunParams rp, const floa
     __shared__ int s_flag;
     __shared__ int s_sweeps;
     __shared__ double s_red[4 * (NT / 64)];
-    extern __shared__ char dyn_lds[];
+    extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
     typename Lds<T>::type *s_sig = as_lds<T>(dyn_lds);
     typename Lds<T>::type *s_mat = as_lds<T>(dyn_lds + rp.lds_mat_off);
     char *wbase = reinterpret_cast<char *>(rp.work) + (long long)blockIdx.x * rp.work_stride;
@@ -1008,7 +1469,9 @@ __global__ __launch_bounds__(NT) void warm_start_kernel(RunParams rp, const floa
         T *g1 = Tm + (long long)P.nmax * P.nmax, *g2 = g1 + (long long)P.nmax * P.nmax;
         for (int pass = 0; pass < 2; ++pass) {
             T *blk = (pass == 0 ? u : v) + off;   // projected in place via the scratch wx
-            if (N <= rp.lpj_nmax) {
+            if (N <= rp.lpj_nmax && rp.eig_wave == 2) {
+                project_block_rows<T, NT>(blk, wx, N, nullptr, false, s_mat, Tm, sc, rp.max_sweeps);
+            } else if (N <= rp.lpj_nmax) {
                 if ((threadIdx.x >> 6) == 0) {
                     const int ldp = lpj_ld(N, (int)sizeof(T));
                     project_block_wave<T>(blk, wx, N, nullptr, false, s_mat, s_mat + (long long)N * ldp, ldp, Tm, s_sig,
@@ -1104,7 +1567,7 @@ __global__ void reset_state(const ProbDesc *probs, int count) {
 // Dynamic LDS layout for element type T: sigma, then G and V (both N x N) for blocks up to
 // lds_nmax, or G alone for blocks up to lds_nmax_g; larger blocks work in global scratch.
 template <typename T>
-void lds_layout(int eig_ld, int lds_budget, int &mat_off, int &lds_nmax, int &lds_nmax_g, size_t &bytes,
+void lds_layout(int eig_ld, int lds_budget, int nw, int &mat_off, int &lds_nmax, int &lds_nmax_g, size_t &bytes,
                 int use_lpj, int &lpj_nmax) {
     size_t off = sizeof(T) * (size_t)(eig_ld + 1);
     off = (off + 15) & ~(size_t)15;
@@ -1118,19 +1581,31 @@ void lds_layout(int eig_ld, int lds_budget, int &mat_off, int &lds_nmax, int &ld
     const size_t need1 = lds_nmax_g ? off + sizeof(T) * (size_t)lds_nmax_g * lds_nmax_g : off;
     bytes = need2 > need1 ? need2 : need1;
     // one-wavefront form: G and V with the padded leading dimension
+    // one-wavefront form (use_lpj 1) or rows-per-wavefront form (use_lpj 2)
     lpj_nmax = 0;
-    if (use_lpj)
+    size_t need3 = off;
+    if (use_lpj == 1) {
         for (int N = eig_ld; N >= 1 && !lpj_nmax; --N)
             if ((long long)(off + sizeof(T) * 2 * (size_t)N * lpj_ld(N, (int)sizeof(T))) <= lds_budget) lpj_nmax = N;
-    const size_t need3 = lpj_nmax ? off + sizeof(T) * 2 * (size_t)lpj_nmax * lpj_ld(lpj_nmax, (int)sizeof(T)) : off;
+        if (lpj_nmax) need3 = off + sizeof(T) * 2 * (size_t)lpj_nmax * lpj_ld(lpj_nmax, (int)sizeof(T));
+    } else if (use_lpj == 2) {
+        for (int N = eig_ld; N >= 1 && !lpj_nmax; --N)
+            if ((long long)(off + sizeof(T) * (size_t)rows_region(N, (int)sizeof(T), nw)) <= lds_budget) lpj_nmax = N;
+        if (lpj_nmax) need3 = off + sizeof(T) * (size_t)rows_region(lpj_nmax, (int)sizeof(T), nw);
+    }
     if (need3 > bytes) bytes = need3;
+    // the affine step's k-vector and partial sums alias the eigen region
+    const size_t need_z = off + sizeof(double) * 2 * SOS_KMAX_LDS;
+    if (need_z > bytes) bytes = need_z;
+    // blocks side by side may use the whole budget
+    if (use_lpj == 1 && lpj_nmax && (size_t)lds_budget > bytes) bytes = (size_t)lds_budget;
 }
 
 template <typename T, int NT>
 int launch_t(int grid, const RunParams &rp_in, hipStream_t st) {
     RunParams rp = rp_in;
     size_t lds = 0;
-    lds_layout<T>(rp.eig_ld, rp.lds_budget, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds, rp.eig_wave,
+    lds_layout<T>(rp.eig_ld, rp.lds_budget, NT / 64, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds, rp.eig_wave,
                   rp.lpj_nmax);
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&admm_persistent<T, NT>),
@@ -1203,7 +1678,8 @@ int sos_launch_warm_start(int fp64, int threads, int grid, const RunParams &rp_i
     (void)hipGetLastError();
 #define SOS_WS(TT, NTT)                                                                                          \
     {                                                                                                           \
-        lds_layout<TT>(rp.eig_ld, rp.lds_budget, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds, rp.eig_wave,  \
+        lds_layout<TT>(rp.eig_ld, rp.lds_budget, NTT / 64, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds,      \
+                       rp.eig_wave,                                                                             \
                        rp.lpj_nmax);                                                                            \
         if (lds > 64 * 1024) {                                                                                  \
             (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&warm_start_kernel<TT, NTT>),               \

@@ -4,7 +4,8 @@ The network and the solver run in libsos.so: this module moves arrays between th
 
 1. Training data: the solver's own batched cold solves of the training instances;
    sos_batch_export_solutions writes each converged (xi / tau, y / tau) in the
-   library's layout, and only instances the solver reports SOLVED are kept.
+   library's layout; instances the solver reports SOLVED are kept, minus those whose
+   solution norm is far above the median (training_mask).
 2. Training: the device MLP (sos_mlp_*) on standardised targets, mini-batch Adam.
    The standardisation (per-output mean and spread of the training targets) is data
    preparation done once; the network's output layer undoes it on the device.
@@ -21,6 +22,17 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 from . import binding as B
+
+
+def training_mask(T, factor: float = 3.0):
+    """Rows of the exported solutions that train the model: those whose norm is at most
+    `factor` times the median norm.  Instances close to infeasibility end with a tiny tau,
+    so their normalised solutions are huge (norms up to hundreds of times the median);
+    left in, they dominate the target statistics and the network predicts neither them
+    nor the rest."""
+    import torch
+    nrm = torch.linalg.vector_norm(T.double(), dim=1)
+    return nrm <= factor * nrm.median()
 
 
 def export_solutions(batch: "B.Batch", layout: int):
@@ -91,14 +103,20 @@ class WarmStartModel:
         return out
 
 
+LAST_FIRST_PASS: List[dict] = []   # infos of the warm-started pass of the last warm_solve call
+LAST_FALLBACK: dict = {}           # the last call's cold fallback: infos and launch times
+
+
 def warm_solve(batch: "B.Batch", model: WarmStartModel, X, fallback_works: Optional[Sequence["B.Work"]] = None,
-               layout: Optional[int] = None):
-    """Predict, warm start, solve; re-solve cold every problem the warm start left unsolved.
+               layout: Optional[int] = None, schedule: Optional[str] = None):
+    """Predict, warm start, solve (with the batch's own iteration budget); re-solve cold,
+    with the fallback handles' budget, every problem the warm start left unsolved.
 
     Returns (infos, n_fallback, ms) with ms the device time of inference + warm start +
     solve + fallback solves."""
     import torch
     layout = layout or model.n_out
+    LAST_FALLBACK.clear()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -107,13 +125,17 @@ def warm_solve(batch: "B.Batch", model: WarmStartModel, X, fallback_works: Optio
     torch.cuda.synchronize()
     B.sos_batch_warm_start(batch, pred, layout)
     infos = B.sos_batch_solve(batch)
+    LAST_FIRST_PASS[:] = [dict(i) for i in infos]
     bad = [i for i, inf in enumerate(infos) if inf["status"] not in (B.SOS_SOLVED, B.SOS_PRIMAL_INFEASIBLE,
                                                                      B.SOS_DUAL_INFEASIBLE)]
     if bad and fallback_works is not None:
         sub = [fallback_works[i] for i in bad]
-        fb = B.sos_batch_setup(sub, None)
+        fb = B.sos_batch_setup(sub, schedule)
         B.sos_batch_reset(fb)
         finfos = B.sos_batch_solve(fb)
+        LAST_FALLBACK.clear()
+        LAST_FALLBACK.update(infos=[dict(f) for f in finfos], idx=list(bad),
+                             phase_ms=(B.sos_batch_phase_ms(fb, 0), B.sos_batch_phase_ms(fb, 1)))
         for i, inf in zip(bad, finfos):
             inf["fallback"] = True
             infos[i] = inf

@@ -98,9 +98,11 @@ def test_learned_warm_start_gain(env):
     tw = [B.setup_problem(F.lyapunov(s), st) for s in train]
     infos, sol, bt = W.cold_solve_batch(tw)
     keep = [i for i, inf in enumerate(infos) if inf["status"] == B.SOS_SOLVED]
-    print(f"[warm] training set: {len(keep)}/{len(train)} solved cold", flush=True)
     Xtr = _dev(torch, np.stack([F.lyapunov_features(train[i]) for i in keep]))
     Ttr = sol[torch.tensor(keep, device="cuda")].contiguous()
+    mask = W.training_mask(Ttr)
+    Xtr, Ttr = Xtr[mask].contiguous(), Ttr[mask].contiguous()
+    print(f"[warm] training set: {len(keep)}/{len(train)} solved cold, {int(mask.sum())} kept", flush=True)
     model = W.WarmStartModel(Xtr.shape[1], Ttr.shape[1], hidden=512, max_batch=4096, seed=0)
     losses = model.fit(Xtr, Ttr, epochs=60, batch=128, lr=1e-3, log=lambda m: print(m, flush=True))
     assert losses[-1] < 0.5 * losses[0]
@@ -112,11 +114,17 @@ def test_learned_warm_start_gain(env):
     wb = B.sos_batch_setup(warm_w)
     Xte = _dev(torch, np.stack([F.lyapunov_features(s) for s in test]))
     winfos, nfb, ms = W.warm_solve(wb, model, Xte, fallback_works=warm_w)
-    ci = np.array([i["iters"] for i in cinfos])
-    wi = np.array([i["iters"] for i in winfos])
+    first = W.LAST_FIRST_PASS
+    both = [i for i in range(len(test)) if cinfos[i]["status"] == B.SOS_SOLVED and first[i]["status"] == B.SOS_SOLVED]
+    ci = np.array([cinfos[i]["iters"] for i in both])
+    wi = np.array([first[i]["iters"] for i in both])
     same = sum(a["status"] == b["status"] for a, b in zip(cinfos, winfos))
-    print(f"[warm] held-out: cold mean iters {ci.mean():.1f} median {np.median(ci):.0f}; warm mean {wi.mean():.1f} "
-          f"median {np.median(wi):.0f}; fallbacks {nfb}; same status {same}/{len(test)}", flush=True)
+    print(f"[warm] held-out, {len(both)} solved both ways: cold mean iters {ci.mean():.1f} median {np.median(ci):.0f}; "
+          f"warm mean {wi.mean():.1f} median {np.median(wi):.0f}; fallbacks {nfb}; same status {same}/{len(test)}",
+          flush=True)
+    # the gain: the trained network's start saves iterations on the problems both starts solve
+    assert len(both) >= len(test) - 6
+    assert wi.mean() <= 0.85 * ci.mean()
     for inf in winfos:
         assert inf["status"] in (B.SOS_SOLVED, B.SOS_PRIMAL_INFEASIBLE, B.SOS_DUAL_INFEASIBLE, B.SOS_MAX_ITERS)
         if inf["status"] == B.SOS_SOLVED:
