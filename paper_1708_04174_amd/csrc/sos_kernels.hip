@@ -322,16 +322,6 @@ __device__ __forceinline__ float wave_allsum(float x) {
     return __shfl(x, 0, 64);
 }
 
-// Wave maximum, lane 0's result broadcast (uniform across the wave).
-template <typename T>
-__device__ __forceinline__ T wave_allmax(T x) {
-    for (int off = 32; off > 0; off >>= 1) {
-        const T y = __shfl_down(x, off, 64);
-        x = y > x ? y : x;
-    }
-    return __shfl(x, 0, 64);
-}
-
 // Sum over a group of GS consecutive lanes; every lane of the group gets the group's first
 // lane's result, so branches on it are uniform inside the group.
 template <int GS, typename T>
@@ -744,8 +734,7 @@ __device__ __noinline__ void project_block_wave(T *__restrict__ vs, T *__restric
     const int H = M / 2;
     int nsw = 0;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        int rotated = 0;
-        T mr = (T)0;   // largest squared relative coupling ga^2 / (al be) rotated away in this sweep
+        int rotated = 0, big = 0;   // big: some rotation of the sweep had coupling above sqrt(tol)
         for (int r = 0; r < M - 1; ++r) {
             for (int kk = lane; kk < H; kk += 64) {
                 // round-robin pair without ordering p < q (the rotation does not need it):
@@ -776,10 +765,7 @@ __device__ __noinline__ void project_block_wave(T *__restrict__ vs, T *__restric
                 const T al = hsum<T>(sa), be = hsum<T>(sb), ga = hsum<T>(sg);
                 T cc, ss;
                 if (!jacobi_rot<T>(al, be, ga, tol2, atol2, cc, ss)) continue;
-                {
-                    const T r2 = ga * ga / (al * be);
-                    mr = r2 > mr ? r2 : mr;
-                }
+                if (ga * ga > tol * (al * be)) big = 1;
                 LVT *vp = (LVT *)(V + p * ld), *vq = (LVT *)(V + q * ld);
                 // software pipelined: the next chunk is read before the current one is written
                 // (columns p and q are distinct, so the two never overlap)
@@ -813,7 +799,7 @@ __device__ __noinline__ void project_block_wave(T *__restrict__ vs, T *__restric
         // converged: no rotation, or every rotation of the sweep was small (relative
         // coupling <= sqrt(tol)); cyclic Jacobi converges quadratically, so what such a
         // sweep leaves is coupling of order tol, which the next sweep would not rotate
-        if (!__any(rotated) || wave_allmax(mr) <= tol) break;
+        if (!__any(rotated) || !__any(big)) break;
     }
     if (lane == 0) atomicAdd(sweeps, nsw);
     for (int j = lane; j < N; j += 64) {
@@ -894,15 +880,20 @@ __host__ __device__ __forceinline__ int rows_ld(int N, int elem_bytes, int nw) {
     const int np = nw * rows_R(N, elem_bytes, nw);
     return q * ((np - r + q - 1) / q) + r;
 }
-// column pairs per round, rounded up to 16
-__host__ __device__ __forceinline__ int rows_hp(int N) {
-    const int H = (N + (N & 1)) / 2;
-    return (H + 15) / 16 * 16;
-}
-// LDS elements of one block: G, V, two buffers of 3 x nw x hp partial sums, sigma
+// column pairs per round
+__host__ __device__ __forceinline__ int rows_hp(int N) { return (N + (N & 1)) / 2; }
+// partial sums (al, be, ga) of one pair and one wavefront: one 16-byte record in FP32,
+// two in FP64; records of a pair padded to nw + 1, so lanes on consecutive pairs read
+// distinct bank groups
+__host__ __device__ __forceinline__ int rows_rec(int elem_bytes) { return elem_bytes == 4 ? 1 : 2; }
+// LDS elements of one block: G, V, two buffers of partial records, sigma
 __host__ __device__ __forceinline__ long long rows_region(int N, int elem_bytes, int nw) {
-    return 2LL * N * rows_ld(N, elem_bytes, nw) + 2LL * 3 * nw * rows_hp(N) + ((N + 3) & ~3);
+    const int vw = 16 / elem_bytes;
+    return 2LL * N * rows_ld(N, elem_bytes, nw) + 2LL * rows_hp(N) * (nw + 1) * rows_rec(elem_bytes) * vw +
+           ((N + 3) & ~3);
 }
+// most 16-byte vectors per column and wavefront held in registers through a round
+template <typename T> struct RowsCache { static constexpr int n = 6; };
 
 template <typename T, int NT>
 __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restrict__ us, int N, T *__restrict__ Vs,
@@ -929,9 +920,10 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
     const int ld = rows_ld(N, (int)sizeof(T), NW);
     const int HP = rows_hp(N);
     const int Np = NW * R;
+    constexpr int REC = sizeof(T) == 4 ? 1 : 2;   // 16-byte records per partial (al, be, ga)
     LT *V = G + (long long)N * ld;
-    LT *part = V + (long long)N * ld;   // [2][3][NW][HP]
-    LT *sig = part + 2 * 3 * NW * HP;
+    LT *part = V + (long long)N * ld;   // [2][HP][NW + 1][REC] records
+    LT *sig = part + 2LL * HP * (NW + 1) * REC * VW;
     double fro2 = 0.0, dummy = 0.0;
     for (int idx = tid; idx < N * N; idx += NT) {
         const int j = idx / N, i = idx - (idx / N) * N;
@@ -989,13 +981,17 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
     const int H = M / 2;
     const int nvw = R / VW;              // vectors per column in this wavefront's rows
     const int row0 = w * R;
+    constexpr int NC = RowsCache<T>::n;
+    const bool cache = nvw <= NC;        // columns of the lane's first pair stay in registers
+    LVT *const partv = (LVT *)part;
     int nsw = 0, round = 0;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        int rotated = 0;
-        T mr = (T)0;   // largest squared relative coupling ga^2 / (al be) rotated away in this sweep
+        int rotated = 0, big = 0;   // big: some rotation of the sweep had coupling above sqrt(tol)
         for (int r = 0; r < M - 1; ++r, ++round) {
-            LT *pb = part + (round & 1) * 3 * NW * HP;
-            // partial inner products over this wavefront's rows
+            LVT *pb = partv + (long long)(round & 1) * HP * (NW + 1) * REC;
+            // pair kk of the round (no ordering p < q needed): lanes on consecutive kk touch
+            // consecutive columns r + kk and r - kk
+            VT cA[NC], cB[NC], cC[NC], cD[NC];   // this wavefront's rows of g_p, g_q, v_p, v_q (first pair)
             for (int kk = lane; kk < H; kk += 64) {
                 int p, q;
                 if (kk == 0) {
@@ -1011,20 +1007,54 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
                 if (p < N && q < N) {
                     const LVT *gp = (const LVT *)(G + p * ld + row0), *gq = (const LVT *)(G + q * ld + row0);
                     VT sa = (VT)(T)0, sb = (VT)(T)0, sg = (VT)(T)0;
+                    if (cache && kk < 64) {
+                        // all of this wavefront's rows of the four columns in one burst of reads
+                        const LVT *vp = (const LVT *)(V + p * ld + row0), *vq = (const LVT *)(V + q * ld + row0);
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            if (c < nvw) {
+                                cA[c] = gp[c];
+                                cB[c] = gq[c];
+                                cC[c] = vp[c];
+                                cD[c] = vq[c];
+                            }
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            if (c < nvw) {
+                                sa += cA[c] * cA[c];
+                                sb += cB[c] * cB[c];
+                                sg += cA[c] * cB[c];
+                            }
+                    } else {
 #pragma unroll 2
-                    for (int c = 0; c < nvw; ++c) {
-                        const VT a = gp[c], b = gq[c];
-                        sa += a * a;
-                        sb += b * b;
-                        sg += a * b;
+                        for (int c = 0; c < nvw; ++c) {
+                            const VT a = gp[c], b = gq[c];
+                            sa += a * a;
+                            sb += b * b;
+                            sg += a * b;
+                        }
                     }
                     al = hsum<T>(sa);
                     be = hsum<T>(sb);
                     ga = hsum<T>(sg);
                 }
-                pb[(0 * NW + w) * HP + kk] = al;
-                pb[(1 * NW + w) * HP + kk] = be;
-                pb[(2 * NW + w) * HP + kk] = ga;
+                LVT *rec = pb + ((long long)kk * (NW + 1) + w) * REC;
+                if constexpr (REC == 1) {
+                    VT x;
+                    x[0] = al;
+                    x[1] = be;
+                    x[2] = ga;
+                    x[3] = (T)0;
+                    rec[0] = x;
+                } else {
+                    VT x0, x1;
+                    x0[0] = al;
+                    x0[1] = be;
+                    x1[0] = ga;
+                    x1[1] = (T)0;
+                    rec[0] = x0;
+                    rec[1] = x1;
+                }
             }
             __syncthreads();
             for (int kk = lane; kk < H; kk += 64) {
@@ -1039,42 +1069,67 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
                     if (q < 0) q += M - 1;
                 }
                 if (p >= N || q >= N) continue;
+                // the NW partial records of pair kk, summed in wavefront order (all wavefronts alike)
+                const LVT *rk = pb + (long long)kk * (NW + 1) * REC;
                 T al = 0, be = 0, ga = 0;
+                if constexpr (REC == 1) {
+                    VT x[NW];
 #pragma unroll
-                for (int x = 0; x < NW; ++x) {
-                    al += pb[(0 * NW + x) * HP + kk];
-                    be += pb[(1 * NW + x) * HP + kk];
-                    ga += pb[(2 * NW + x) * HP + kk];
+                    for (int y = 0; y < NW; ++y) x[y] = rk[y];
+#pragma unroll
+                    for (int y = 0; y < NW; ++y) {
+                        al += x[y][0];
+                        be += x[y][1];
+                        ga += x[y][2];
+                    }
+                } else {
+                    VT x[2 * NW];
+#pragma unroll
+                    for (int y = 0; y < 2 * NW; ++y) x[y] = rk[y];
+#pragma unroll
+                    for (int y = 0; y < NW; ++y) {
+                        al += x[2 * y][0];
+                        be += x[2 * y][1];
+                        ga += x[2 * y + 1][0];
+                    }
                 }
                 T cc, ss;
                 if (!jacobi_rot<T>(al, be, ga, tol2, atol2, cc, ss)) continue;
-                {
-                    const T r2 = ga * ga / (al * be);
-                    mr = r2 > mr ? r2 : mr;
-                }
+                if (ga * ga > tol * (al * be)) big = 1;
                 LVT *gp = (LVT *)(G + p * ld + row0), *gq = (LVT *)(G + q * ld + row0);
                 LVT *vp = (LVT *)(V + p * ld + row0), *vq = (LVT *)(V + q * ld + row0);
-                // one 16-byte vector per column at a time, the next one read before the
-                // current one is written (columns p and q are distinct, so they never overlap)
-                VT A = gp[0], Bv = gq[0], C = vp[0], D = vq[0];
-                for (int c = 0; c < nvw; ++c) {
-                    VT nA, nB, nC, nD;
-                    const bool more = c + 1 < nvw;
-                    if (more) {
-                        nA = gp[c + 1];
-                        nB = gq[c + 1];
-                        nC = vp[c + 1];
-                        nD = vq[c + 1];
-                    }
-                    gp[c] = cc * A - ss * Bv;
-                    gq[c] = ss * A + cc * Bv;
-                    vp[c] = cc * C - ss * D;
-                    vq[c] = ss * C + cc * D;
-                    if (more) {
-                        A = nA;
-                        Bv = nB;
-                        C = nC;
-                        D = nD;
+                if (cache && kk < 64) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        if (c < nvw) {
+                            gp[c] = cc * cA[c] - ss * cB[c];
+                            gq[c] = ss * cA[c] + cc * cB[c];
+                            vp[c] = cc * cC[c] - ss * cD[c];
+                            vq[c] = ss * cC[c] + cc * cD[c];
+                        }
+                } else {
+                    // one 16-byte vector per column at a time, the next one read before the
+                    // current one is written (columns p and q are distinct, so they never overlap)
+                    VT A = gp[0], Bv = gq[0], C = vp[0], D = vq[0];
+                    for (int c = 0; c < nvw; ++c) {
+                        VT nA, nB, nC, nD;
+                        const bool more = c + 1 < nvw;
+                        if (more) {
+                            nA = gp[c + 1];
+                            nB = gq[c + 1];
+                            nC = vp[c + 1];
+                            nD = vq[c + 1];
+                        }
+                        gp[c] = cc * A - ss * Bv;
+                        gq[c] = ss * A + cc * Bv;
+                        vp[c] = cc * C - ss * D;
+                        vq[c] = ss * C + cc * D;
+                        if (more) {
+                            A = nA;
+                            Bv = nB;
+                            C = nC;
+                            D = nD;
+                        }
                     }
                 }
                 rotated = 1;
@@ -1083,9 +1138,11 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
             wave_fence_sync();
         }
         ++nsw;
-        // every wavefront took the same decisions, so the vote needs no exchange; converged
-        // as in the one-wavefront form (no rotation, or all rotations of the sweep small)
-        if (!__any(rotated) || wave_allmax(mr) <= tol) break;
+        // every wavefront took the same decisions, so the vote needs no exchange.  Converged:
+        // no rotation, or every rotation of the sweep was small (relative coupling at most
+        // sqrt(tol)); cyclic Jacobi converges quadratically, so such a sweep leaves coupling
+        // of order tol, which the next sweep would not rotate
+        if (!__any(rotated) || !__any(big)) break;
     }
     if (tid == 0) *sc.s_sweeps += nsw;
     __syncthreads();
