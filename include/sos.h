@@ -92,7 +92,13 @@ typedef struct {
     int32_t precision;       /* SOS_FP64 | SOS_FP32_MIXED */
     int32_t polish_iters;    /* FP64 iterations after an FP32 solve (>= 1 for SOS_FP32_MIXED) */
     int32_t partition;       /* SOS_PART_PAPER | SOS_PART_COLUMNS */
-    int32_t block_threads;   /* threads per workgroup: 0 = default (256), else 64..1024, multiple of 64 */
+    int32_t block_threads;   /* threads per workgroup: 0 = default (512), else 64..1024, multiple of 64 */
+    int32_t warm_budget;     /* 0: a warm-started solve keeps its start to the end.  > 0: a solve that
+                                starts from sos_warm_start / sos_batch_warm_start and has neither
+                                converged after warm_budget iterations nor kept tau > 0 at a residual
+                                check is restarted in the same launch from the cold start with the
+                                full max_iters budget (cold ADMM as the fallback); the abandoned
+                                iterations are reported in sos_info.warm_iters */
 } sos_settings;
 
 typedef struct {
@@ -107,6 +113,8 @@ typedef struct {
     double  setup_ms, solve_ms;
     double  eig_sweeps;      /* mean eigensolver sweeps per block projection in the last launch */
     double  affine_ms, eig_ms, resid_ms;   /* device time of the last launch by phase (one workgroup's clock) */
+    int32_t warm_iters;      /* iterations of a warm-started attempt abandoned for the cold restart
+                                (0: no restart; then iters counts the warm-started run itself) */
 } sos_info;
 
 /* Fills *s with tol 1e-4, max_iters 2000, check_every 10, alpha 1, SOS_FP64,

@@ -49,7 +49,7 @@ class sos_cone(C.Structure):
 class sos_settings(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int32), ("check_every", C.c_int32),
                 ("alpha", C.c_double), ("precision", C.c_int32), ("polish_iters", C.c_int32),
-                ("partition", C.c_int32), ("block_threads", C.c_int32)]
+                ("partition", C.c_int32), ("block_threads", C.c_int32), ("warm_budget", C.c_int32)]
 
 
 class sos_info(C.Structure):
@@ -58,7 +58,7 @@ class sos_info(C.Structure):
                 ("res_pri", C.c_double), ("res_dual", C.c_double), ("gap", C.c_double),
                 ("tau", C.c_double), ("kappa", C.c_double), ("setup_ms", C.c_double),
                 ("solve_ms", C.c_double), ("eig_sweeps", C.c_double), ("affine_ms", C.c_double),
-                ("eig_ms", C.c_double), ("resid_ms", C.c_double)]
+                ("eig_ms", C.c_double), ("resid_ms", C.c_double), ("warm_iters", C.c_int32)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}

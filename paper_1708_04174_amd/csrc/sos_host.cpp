@@ -135,6 +135,7 @@ void default_settings(sos_settings *s) {
     s->polish_iters = 1;
     s->partition = SOS_PART_PAPER;
     s->block_threads = 0;
+    s->warm_budget = 0;
 }
 
 void check_settings(const sos_settings &s) {
@@ -145,6 +146,7 @@ void check_settings(const sos_settings &s) {
     if (s.block_threads != 0 && (s.block_threads < 64 || s.block_threads > 1024 || (s.block_threads & (s.block_threads - 1))))
         throw Status(SOS_E_INVAL, "block_threads must be 0 or a power of two in 64..1024");
     if (s.precision == SOS_FP32_MIXED && s.polish_iters < 1) throw Status(SOS_E_INVAL, "polish_iters >= 1 required");
+    if (s.warm_budget < 0) throw Status(SOS_E_INVAL, "warm_budget must be >= 0");
 }
 
 // Dense Cholesky of the k x k SPD matrix S (row-major), lower factor in place.
@@ -549,6 +551,7 @@ void read_info(sos_work *w, const double *o, sos_info *info, int iters, int poli
     info->affine_ms = o[SOS_OUT_T_AFFINE] / khz;
     info->eig_ms = o[SOS_OUT_T_EIG] / khz;
     info->resid_ms = o[SOS_OUT_T_RES] / khz;
+    info->warm_iters = (int)o[SOS_OUT_WARM];
 }
 
 template <typename F>
@@ -612,14 +615,16 @@ void fetch_state(const sos_work *w, std::vector<double> &u, std::vector<double> 
     hip_check(hipStreamSynchronize(w->stream), "sync");
 }
 
-void push_state(sos_work *w, const std::vector<double> &u, const std::vector<double> &v, const double tk[2]) {
+void push_state(sos_work *w, const std::vector<double> &u, const std::vector<double> &v, const double tk[2],
+                bool warm_start = false) {
     const int nu = w->nx + w->m, nv = w->nx;
     std::vector<float> uf(u.begin(), u.end()), vf(v.begin(), v.end());
     hip_check(hipMemcpyAsync(w->desc.u64, u.data(), nu * sizeof(double), hipMemcpyHostToDevice, w->stream), "copy");
     hip_check(hipMemcpyAsync(w->desc.v64, v.data(), nv * sizeof(double), hipMemcpyHostToDevice, w->stream), "copy");
     hip_check(hipMemcpyAsync(w->desc.u32, uf.data(), nu * sizeof(float), hipMemcpyHostToDevice, w->stream), "copy");
     hip_check(hipMemcpyAsync(w->desc.v32, vf.data(), nv * sizeof(float), hipMemcpyHostToDevice, w->stream), "copy");
-    const double tk4[4] = {tk[0], tk[1], 0.0, 0.0};   // new iterate: cached eigenvectors are stale
+    // new iterate: cached eigenvectors are stale; a warm start is judged by the next solve
+    const double tk4[4] = {tk[0], tk[1], 0.0, warm_start ? 1.0 : 0.0};
     hip_check(hipMemcpyAsync(w->desc.tk, tk4, sizeof(tk4), hipMemcpyHostToDevice, w->stream), "copy");
     hip_check(hipStreamSynchronize(w->stream), "sync");
     w->active64 = true;
@@ -669,7 +674,7 @@ int sos_setup(const sos_csc *A, const double *b, const double *c, const sos_cone
     const auto t0 = std::chrono::steady_clock::now();
     int rc = guarded(w, [&] {
         check_settings(w->st);
-        w->threads = w->st.block_threads ? w->st.block_threads : 256;
+        w->threads = w->st.block_threads ? w->st.block_threads : 512;
         build(w, A, b, c, K);
     });
     if (rc != SOS_OK) {
@@ -709,7 +714,9 @@ int sos_solve(sos_work *w, sos_info *info) {
         hip_check(hipEventRecord(w->ev0, w->stream), "event");
         if (w->st.precision == SOS_FP64) {
             set_active(w, true);
-            run_single(w, 1, single_params(w, RUN_SOLVE, w->st.max_iters, 0, w->st.tol));
+            RunParams r = single_params(w, RUN_SOLVE, w->st.max_iters, 0, w->st.tol);
+            r.warm_budget = w->st.warm_budget;
+            run_single(w, 1, r);
             hip_check(hipMemcpyAsync(o, w->desc.out, sizeof(o), hipMemcpyDeviceToHost, w->stream), "copy");
             hip_check(hipStreamSynchronize(w->stream), "sync");
             total = (int)o[SOS_OUT_ITERS];
@@ -718,6 +725,7 @@ int sos_solve(sos_work *w, sos_info *info) {
             set_active(w, false);
             RunParams r32 = single_params(w, RUN_SOLVE, w->st.max_iters, 0, w->st.tol);
             r32.stall_checks = kStallChecks;
+            r32.warm_budget = w->st.warm_budget;
             run_single(w, 0, r32);
             set_active(w, true);
             RunParams r64 = single_params(w, RUN_SOLVE, w->st.max_iters, w->st.polish_iters, w->st.tol);
@@ -759,7 +767,7 @@ int sos_warm_start(sos_work *w, const double *x, const double *y, const double *
         }
         for (int i = 0; i < w->m; ++i) u[w->nx + i] = tau * y[i];
         const double tk[2] = {tau, kappa};
-        push_state(w, u, v, tk);
+        push_state(w, u, v, tk, true);
     });
 }
 
@@ -844,8 +852,8 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         B->fp64 = B->st.precision == SOS_FP64;
         for (int i = 1; i < count; ++i)
             if (probs[i]->st.precision != B->st.precision) throw Status(SOS_E_INVAL, "mixed precisions in one batch");
-        B->threads = (int)json_num(schedule_json, "block_threads", B->st.block_threads ? B->st.block_threads : 256);
-        B->wg_per_cu = (int)json_num(schedule_json, "wg_per_cu", 2);
+        B->threads = (int)json_num(schedule_json, "block_threads", B->st.block_threads ? B->st.block_threads : 512);
+        B->wg_per_cu = (int)json_num(schedule_json, "wg_per_cu", 1);
         B->max_sweeps = (int)json_num(schedule_json, "max_sweeps", 60);
         B->use_graph = json_num(schedule_json, "use_graph", 1) != 0.0;
         B->warm_eig = (int)json_num(schedule_json, "warm_eig", 1);
@@ -943,12 +951,14 @@ static void enqueue_batch(sos_batch *B) {
     if (sos_launch_reset(B->d_counter, B->stream, B->d_ts)) throw Status(SOS_E_HIP, "reset launch failed");
     if (B->fp64) {
         RunParams rp = batch_params(B, RUN_SOLVE, B->st.max_iters, 0, B->st.tol);
+        rp.warm_budget = B->st.warm_budget;
         rp.ts = B->d_ts;
         if (sos_launch_admm(1, B->threads, B->grid, rp, B->stream)) throw Status(SOS_E_HIP, "launch failed");
     } else {
         // FP32 phase: to tol, or until it stops improving; then FP64 for the rest of the budget
         RunParams rp = batch_params(B, RUN_SOLVE, B->st.max_iters, 0, B->st.tol);
         rp.stall_checks = kStallChecks;
+        rp.warm_budget = B->st.warm_budget;
         rp.ts = B->d_ts;
         if (sos_launch_admm(0, B->threads, B->grid, rp, B->stream)) throw Status(SOS_E_HIP, "launch failed");
         if (sos_launch_cast_state(B->d_desc, nullptr, B->count, 1, B->stream, B->max_len))

@@ -51,7 +51,8 @@ struct ProbDesc {
     // iterate
     double *u64, *v64;
     float  *u32, *v32;
-    double *tk;          // [0] tau, [1] kappa, [2] 1 if vs holds eigenvectors of the last iteration
+    double *tk;          // [0] tau, [1] kappa, [2] 1 if vs holds eigenvectors of the last iteration,
+                         // [3] 1 while the iterate is a warm start not yet judged
     double *vs64;        // per PSD block, its N x N eigenvectors from the last iteration (Jacobi warm start)
     float *vs32;
     double *out;         // SOS_OUT_* below
@@ -59,7 +60,7 @@ struct ProbDesc {
 
 enum {
     SOS_OUT_STATUS = 0, SOS_OUT_ITERS, SOS_OUT_POBJ, SOS_OUT_DOBJ, SOS_OUT_RP, SOS_OUT_RD, SOS_OUT_GAP,
-    SOS_OUT_TAU, SOS_OUT_KAPPA, SOS_OUT_CX, SOS_OUT_BY, SOS_OUT_TOTAL, SOS_OUT_SWEEPS, SOS_OUT_T_AFFINE, SOS_OUT_T_EIG, SOS_OUT_T_RES, SOS_OUT_N
+    SOS_OUT_TAU, SOS_OUT_KAPPA, SOS_OUT_CX, SOS_OUT_BY, SOS_OUT_TOTAL, SOS_OUT_SWEEPS, SOS_OUT_T_AFFINE, SOS_OUT_T_EIG, SOS_OUT_T_RES, SOS_OUT_WARM, SOS_OUT_N
 };
 
 enum { RUN_STEP = 0, RUN_SOLVE = 1 };
@@ -85,10 +86,12 @@ struct RunParams {
     int eig_wave;           // blocks that fit in LDS: 1 one-wavefront eigensolver, 2 rows split over wavefronts
     int lds_mat_off, lds_nmax, lds_nmax_g, lpj_nmax;   // filled in by the launcher
     int accumulate;         // 0: out[TOTAL] = iterations of this launch; 1: out[TOTAL] += them, and the
-                            //    iteration budget is iters - out[TOTAL] (at least min_iters)
+                            //    iteration budget is iters + out[WARM] - out[TOTAL] (at least min_iters)
+    int warm_budget;        // > 0 (first launch of a solve): restart a warm start (tk[3] = 1) from the cold
+                            //    start once it reaches this many iterations unsolved or shows tau = 0
     int gs_bucket[7];       // lanes per Jacobi column pair (8, 16 or 32) by block-size bucket:
                             // N < 32, < 64, < 96, < 128, < 192, < 256, >= 256
-    int stall_checks;       // > 0: stop a problem whose residual missed 0.9 x its best this many checks in a row
+    int stall_checks;       // > 0: stop a problem that stopped improving (see the kernel) this many checks in a row
     unsigned long long *ts; // optional [start, end] wall-clock stamps of the launch (min / max over workgroups)
 };
 

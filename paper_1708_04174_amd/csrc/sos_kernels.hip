@@ -1333,9 +1333,12 @@ __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
         // iteration budget: in an accumulating (second) phase, what the first phase left over
         int cap = rp.iters;
         if (rp.accumulate) {
-            cap = rp.iters - (int)P.out[SOS_OUT_TOTAL];
+            cap = rp.iters + (int)P.out[SOS_OUT_WARM] - (int)P.out[SOS_OUT_TOTAL];
             if (cap < rp.min_iters) cap = rp.min_iters;
         }
+        // a warm start under judgement (first launch of a solve only)
+        bool trying = rp.mode == RUN_SOLVE && !rp.accumulate && rp.warm_budget > 0 && P.tk[3] != 0.0;
+        int it_warm = 0;   // iterations of an abandoned warm attempt
         double best = INFINITY, best_ce = INFINITY;
         bool was_cert = false;
         int since_best = 0;
@@ -1429,9 +1432,36 @@ __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
             if (rp.mode == RUN_SOLVE && it >= rp.min_iters &&
                 (it % rp.check_every == 0 || it == cap || it == rp.min_iters)) {
                 double pm[2] = {INFINITY, INFINITY};
-                status = residual_phase<T, NT>(P, rp.tol, s_red, it, pm);
+                status = residual_phase<T, NT>(P, rp.tol, s_red, it_warm + it, pm);
                 t_res += wall_clock64() - t2;
                 if (status) break;
+                if (trying && (!(P.tk[0] > 0.0) || it >= rp.warm_budget)) {
+                    // the warm start failed its trial: restart from the cold start u = v = (0, 0, 1)
+                    // with the full budget (the cold method as the fallback)
+                    __syncthreads();
+                    const int nu = P.nx + P.m;
+                    for (int e = threadIdx.x; e < nu; e += NT) {
+                        u[e] = (T)0;
+                        if (e < P.nx) v[e] = (T)0;
+                    }
+                    if (threadIdx.x == 0) {
+                        P.tk[0] = 1.0;
+                        P.tk[1] = 1.0;
+                        P.tk[2] = 0.0;
+                        P.tk[3] = 0.0;
+                    }
+                    __syncthreads();
+                    trying = false;
+                    warm = false;
+                    it_warm += it;
+                    it = 0;
+                    cap = rp.iters;
+                    best = INFINITY;
+                    best_ce = INFINITY;
+                    was_cert = false;
+                    since_best = 0;
+                    continue;
+                }
                 // a phase that stops improving hands over (the FP32 phase of the mixed form):
                 // stalled once stall_checks checks in a row (three times as many while
                 // tau = 0) missed 0.99 x the best value of the measure of the current
@@ -1461,7 +1491,7 @@ __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
             }
         }
         if (rp.mode == RUN_STEP || status == 0) {
-            status = residual_phase<T, NT>(P, rp.tol, s_red, it);
+            status = residual_phase<T, NT>(P, rp.tol, s_red, it_warm + it);
             if (rp.mode == RUN_SOLVE && status == 0 && !stalled && threadIdx.x == 0) P.out[SOS_OUT_STATUS] = 4;
         }
         if (threadIdx.x == 0) {
@@ -1469,8 +1499,10 @@ __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
             P.out[SOS_OUT_T_EIG] = (double)t_eig;
             P.out[SOS_OUT_T_RES] = (double)t_res;
             P.out[SOS_OUT_SWEEPS] = (it > 0 && P.nblk > 0) ? (double)s_sweeps / ((double)it * P.nblk) : 0.0;
-            P.out[SOS_OUT_TOTAL] = (rp.accumulate ? P.out[SOS_OUT_TOTAL] : 0.0) + it;
+            P.out[SOS_OUT_TOTAL] = (rp.accumulate ? P.out[SOS_OUT_TOTAL] : 0.0) + it_warm + it;
+            if (!rp.accumulate) P.out[SOS_OUT_WARM] = it_warm;
             if (it > 0) P.tk[2] = rp.warm_eig ? 1.0 : 0.0;
+            if (rp.mode == RUN_SOLVE) P.tk[3] = 0.0;   // judged (or never under judgement)
         }
         __syncthreads();
     }
@@ -1553,6 +1585,7 @@ __global__ __launch_bounds__(NT) void warm_start_kernel(RunParams rp, const floa
         P.tk[0] = 1.0;
         P.tk[1] = 0.0;
         P.tk[2] = 0.0;
+        P.tk[3] = 1.0;   // a warm start, to be judged by the next solve
     }
     __syncthreads();
     }
@@ -1618,6 +1651,7 @@ __global__ void reset_state(const ProbDesc *probs, int count) {
         P.tk[0] = 1.0;
         P.tk[1] = 1.0;
         P.tk[2] = 0.0;
+        P.tk[3] = 0.0;
     }
 }
 

@@ -12,7 +12,8 @@ The network and the solver run in libsos.so: this module moves arrays between th
 3. Use: predict (xi, y) for new instances, sos_batch_warm_start makes the prediction
    consistent with the cones (u = (P_K(xi), y, 1), v = (P_K*(c - A^T y), 0, 0)), the
    batch is solved, and every problem that the warm start does not bring to a
-   SOLVED status or a certificate is solved again from the cold start (the fallback).
+   SOLVED status or a certificate is solved from the cold start (the fallback): in the
+   same launch when the settings carry a warm_budget, else by a second batched solve.
 """
 from __future__ import annotations
 
@@ -126,8 +127,10 @@ def warm_solve(batch: "B.Batch", model: WarmStartModel, X, fallback_works: Optio
     B.sos_batch_warm_start(batch, pred, layout)
     infos = B.sos_batch_solve(batch)
     LAST_FIRST_PASS[:] = [dict(i) for i in infos]
+    # cold re-solve of what the warm start left unsolved, unless the solve already restarted
+    # it from the cold start in the same launch (warm_budget > 0; warm_iters > 0)
     bad = [i for i, inf in enumerate(infos) if inf["status"] not in (B.SOS_SOLVED, B.SOS_PRIMAL_INFEASIBLE,
-                                                                     B.SOS_DUAL_INFEASIBLE)]
+                                                                     B.SOS_DUAL_INFEASIBLE) and inf["warm_iters"] == 0]
     if bad and fallback_works is not None:
         sub = [fallback_works[i] for i in bad]
         fb = B.sos_batch_setup(sub, schedule)

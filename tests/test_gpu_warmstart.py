@@ -181,3 +181,33 @@ def test_warm_start_kernel_on_more_problems_than_workgroups(env):
         print(f"[warm] problem {idx}: |du| {eu:.1e} |dv| {ev:.1e}", flush=True)
         assert eu < 1e-5 and ev < 1e-5
     bt.free()
+
+
+def test_failed_warm_start_restarts_cold_in_the_same_launch(env):
+    # a useless prediction under a small warm budget: the solve abandons it and restarts from
+    # the cold start, after which it must retrace the cold solve exactly (FP64: bitwise)
+    B, torch = env
+    probs = [F.lyapunov(s) for s in (3584, 3585, 3586)]
+    s_cold = B.sos_default_settings(tol=1e-4, max_iters=2000, precision=B.SOS_FP64)
+    s_warm = B.sos_default_settings(tol=1e-4, max_iters=2000, precision=B.SOS_FP64, warm_budget=20)
+    cold = [B.setup_problem(p, s_cold) for p in probs]
+    warm = [B.setup_problem(p, s_warm) for p in probs]
+    bc = B.sos_batch_setup(cold)
+    B.sos_batch_reset(bc)
+    ci = B.sos_batch_solve(bc)
+    bw = B.sos_batch_setup(warm)
+    L = B.sos_layout_size(warm[0])
+    rng = np.random.default_rng(3)
+    pred = (rng.standard_normal((len(probs), L)) * 50.0).astype(np.float32)
+    B.sos_batch_warm_start(bw, _dev(torch, pred), L)
+    wi = B.sos_batch_solve(bw)
+    for a, b, wk, ck in zip(ci, wi, warm, cold):
+        print(f"[warm] cold {a['status_name']} {a['iters']} it; bad warm start: {b['status_name']} "
+              f"{b['iters']} it of which {b['warm_iters']} abandoned", flush=True)
+        assert b["warm_iters"] > 0 and b["warm_iters"] % 10 == 0
+        assert b["status"] == a["status"] and b["iters"] - b["warm_iters"] == a["iters"]
+        uw, vw = B.sos_get_iterate(wk)
+        uc, vc = B.sos_get_iterate(ck)
+        assert np.array_equal(uw, uc) and np.array_equal(vw, vc)
+    bc.free()
+    bw.free()
