@@ -3,9 +3,11 @@
 Times fixed-length batched runs (the same persistent kernel the solve uses, stopped after
 a fixed number of iterations) and picks
   1. per block-size bucket (N < 32, 64, 96, 128, 192, 256, larger): the lanes that
-     share one Jacobi column pair (8, 16 or 32) - the tile of the eigensolver;
-  2. for the whole batch: threads per workgroup and resident workgroups per CU (which
-     also sets the LDS each workgroup may use).
+     share one Jacobi column pair (8, 16 or 32) in the group form of the eigensolver
+     (blocks too large for the LDS forms);
+  2. for the whole batch: the eigensolver form for blocks that fit in LDS (rows split
+     over the wavefronts, or one wavefront per block), threads per workgroup and
+     resident workgroups per CU (which also sets the LDS each workgroup may use).
 Writes the schedule JSON that sos_batch_setup reads.
 
     python -m paper_1708_04174_amd.autotune --workload lyapunov --out schedules/lyapunov_512.json
@@ -48,7 +50,7 @@ def time_schedule(works, sched: dict, reps: int = 2) -> float:
 def tune(probs, precision: int, iters: int = 40, sample: int = 64, log=print) -> dict:
     # fixed-length runs: an unreachable tolerance makes every problem run `iters` iterations
     st = B.sos_default_settings(tol=1e-14, max_iters=iters, precision=precision, polish_iters=1)
-    base = {"block_threads": 256, "wg_per_cu": 2, "max_sweeps": 60, "warm_eig": 1, "use_graph": 0}
+    base = {"block_threads": 512, "wg_per_cu": 1, "max_sweeps": 60, "warm_eig": 1, "use_graph": 0, "eig_wave": 2}
     byb = defaultdict(list)
     for i, p in enumerate(probs):
         for b in sorted({bucket_of(N) for N in p.psd_dims if N > 1}):
@@ -72,16 +74,15 @@ def tune(probs, precision: int, iters: int = 40, sample: int = 64, log=print) ->
     pick = rng.choice(len(probs), size=min(len(probs), 4 * sample), replace=False)
     works = [B.setup_problem(probs[i], st) for i in pick]
     res = {}
-    for thr in (128, 256, 512):
-        for wpc in (1, 2, 4):
-            if thr * wpc > 1024:
-                continue
-            s = dict(sched)
-            s["block_threads"], s["wg_per_cu"] = thr, wpc
-            res[(thr, wpc)] = time_schedule(works, s)
-            log(f"[tune] threads {thr} wg/CU {wpc}: {res[(thr, wpc)]:.2f} ms")
-    thr, wpc = min(res, key=res.get)
-    sched["block_threads"], sched["wg_per_cu"] = thr, wpc
+    for ew in (2, 1):
+        for thr in (256, 512):
+            for wpc in (1, 2):
+                s = dict(sched)
+                s["eig_wave"], s["block_threads"], s["wg_per_cu"] = ew, thr, wpc
+                res[(ew, thr, wpc)] = time_schedule(works, s)
+                log(f"[tune] eigensolver form {ew} threads {thr} wg/CU {wpc}: {res[(ew, thr, wpc)]:.2f} ms")
+    ew, thr, wpc = min(res, key=res.get)
+    sched["eig_wave"], sched["block_threads"], sched["wg_per_cu"] = ew, thr, wpc
     sched["use_graph"] = 1
     for w in works:
         w.free()
@@ -96,13 +97,15 @@ def main():
     ap.add_argument("--count", type=int, default=512)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--out", required=True)
+    ap.add_argument("--iters", type=int, default=40)
+    ap.add_argument("--sample", type=int, default=64)
     a = ap.parse_args()
     import torch
     assert torch.cuda.is_available()
     seeds = WL.LYAP_TEST if a.workload == "lyapunov" else range(a.count)
     probs = WL.generate(a.workload, list(seeds)[:a.count])
     prec = B.SOS_FP32_MIXED if a.precision == "fp32" else B.SOS_FP64
-    sched = tune(probs, prec, log=lambda m: print(m, file=sys.stderr, flush=True))
+    sched = tune(probs, prec, iters=a.iters, sample=a.sample, log=lambda m: print(m, file=sys.stderr, flush=True))
     with open(a.out, "w") as f:
         json.dump(sched, f, indent=1)
     print(json.dumps(sched))

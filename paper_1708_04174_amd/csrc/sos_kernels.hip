@@ -644,6 +644,11 @@ template <typename T> __device__ __forceinline__ T hsum(typename V16<T>::v x);
 template <> __device__ __forceinline__ float hsum<float>(V16<float>::v x) { return (x.x + x.y) + (x.z + x.w); }
 template <> __device__ __forceinline__ double hsum<double>(V16<double>::v x) { return x.x + x.y; }
 
+// Between Jacobi rounds of one wavefront: a code-motion barrier only.  A wavefront's LDS
+// operations are performed in issue order, so a read issued after a write (by any lane of
+// the same wavefront) returns the written value without waiting for the write to finish.
+__device__ __forceinline__ void wave_order() { __builtin_amdgcn_wave_barrier(); }
+
 __device__ __forceinline__ void wave_fence_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -868,16 +873,32 @@ __device__ __noinline__ void project_block_wave(T *__restrict__ vs, T *__restric
 // decisions, and each rotates its own rows.  No wavefront touches another's rows of G or
 // V; the barrier only guards the partials, which alternate between two buffers by round
 // parity (a wavefront can only be one round ahead of the slowest).
+// Wavefronts that own rows: among the counts up to nw with the fewest rows per wavefront
+// (the latency of a round), the one that pads the fewest rows in total (the LDS traffic);
+// ties keep more wavefronts.  The others only join the barriers.
+__host__ __device__ __forceinline__ int rows_nwe(int N, int elem_bytes, int nw) {
+    const int vw = 16 / elem_bytes;
+    int best = nw, best_r = 1 << 30, best_np = 1 << 30;
+    for (int e = nw; e >= 1; --e) {
+        const int r = ((N + e - 1) / e + vw - 1) / vw * vw;
+        if (r < best_r || (r == best_r && e * r < best_np)) {
+            best_r = r;
+            best_np = e * r;
+            best = e;
+        }
+    }
+    return best;
+}
 __host__ __device__ __forceinline__ int rows_R(int N, int elem_bytes, int nw) {
     const int vw = 16 / elem_bytes;
-    const int r = (N + nw - 1) / nw;
-    return (r + vw - 1) / vw * vw;
+    const int e = rows_nwe(N, elem_bytes, nw);
+    return ((N + e - 1) / e + vw - 1) / vw * vw;
 }
-// leading dimension: at least NW R, and 16 bytes (mod 128): lanes on consecutive columns
+// leading dimension: at least nwe R, and 16 bytes (mod 128): lanes on consecutive columns
 // read distinct 4-bank groups
 __host__ __device__ __forceinline__ int rows_ld(int N, int elem_bytes, int nw) {
     const int q = 128 / elem_bytes, r = 16 / elem_bytes;
-    const int np = nw * rows_R(N, elem_bytes, nw);
+    const int np = rows_nwe(N, elem_bytes, nw) * rows_R(N, elem_bytes, nw);
     return q * ((np - r + q - 1) / q) + r;
 }
 // column pairs per round
@@ -916,10 +937,11 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
         __syncthreads();
         return;
     }
+    const int NWE = rows_nwe(N, (int)sizeof(T), NW);   // wavefronts owning rows
     const int R = rows_R(N, (int)sizeof(T), NW);
     const int ld = rows_ld(N, (int)sizeof(T), NW);
     const int HP = rows_hp(N);
-    const int Np = NW * R;
+    const int Np = NWE * R;
     constexpr int REC = sizeof(T) == 4 ? 1 : 2;   // 16-byte records per partial (al, be, ga)
     LT *V = G + (long long)N * ld;
     LT *part = V + (long long)N * ld;   // [2][HP][NW + 1][REC] records
@@ -981,6 +1003,7 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
     const int H = M / 2;
     const int nvw = R / VW;              // vectors per column in this wavefront's rows
     const int row0 = w * R;
+    const bool owner = w < NWE;          // wavefronts past NWE own no rows: barriers only
     constexpr int NC = RowsCache<T>::n;
     const bool cache = nvw <= NC;        // columns of the lane's first pair stay in registers
     LVT *const partv = (LVT *)part;
@@ -992,7 +1015,7 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
             // pair kk of the round (no ordering p < q needed): lanes on consecutive kk touch
             // consecutive columns r + kk and r - kk
             VT cA[NC], cB[NC], cC[NC], cD[NC];   // this wavefront's rows of g_p, g_q, v_p, v_q (first pair)
-            for (int kk = lane; kk < H; kk += 64) {
+            for (int kk = owner ? lane : H; kk < H; kk += 64) {
                 int p, q;
                 if (kk == 0) {
                     p = r;
@@ -1057,6 +1080,8 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
                 }
             }
             __syncthreads();
+            // every wavefront (owner or not) takes the rotation decisions, so the
+            // convergence vote below is the same in all of them
             for (int kk = lane; kk < H; kk += 64) {
                 int p, q;
                 if (kk == 0) {
@@ -1069,33 +1094,42 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
                     if (q < 0) q += M - 1;
                 }
                 if (p >= N || q >= N) continue;
-                // the NW partial records of pair kk, summed in wavefront order (all wavefronts alike)
+                // the NWE partial records of pair kk, summed in wavefront order (all wavefronts alike)
                 const LVT *rk = pb + (long long)kk * (NW + 1) * REC;
                 T al = 0, be = 0, ga = 0;
                 if constexpr (REC == 1) {
                     VT x[NW];
 #pragma unroll
-                    for (int y = 0; y < NW; ++y) x[y] = rk[y];
+                    for (int y = 0; y < NW; ++y)
+                        if (y < NWE) x[y] = rk[y];
 #pragma unroll
-                    for (int y = 0; y < NW; ++y) {
-                        al += x[y][0];
-                        be += x[y][1];
-                        ga += x[y][2];
-                    }
+                    for (int y = 0; y < NW; ++y)
+                        if (y < NWE) {
+                            al += x[y][0];
+                            be += x[y][1];
+                            ga += x[y][2];
+                        }
                 } else {
                     VT x[2 * NW];
 #pragma unroll
-                    for (int y = 0; y < 2 * NW; ++y) x[y] = rk[y];
+                    for (int y = 0; y < NW; ++y)
+                        if (y < NWE) {
+                            x[2 * y] = rk[2 * y];
+                            x[2 * y + 1] = rk[2 * y + 1];
+                        }
 #pragma unroll
-                    for (int y = 0; y < NW; ++y) {
-                        al += x[2 * y][0];
-                        be += x[2 * y][1];
-                        ga += x[2 * y + 1][0];
-                    }
+                    for (int y = 0; y < NW; ++y)
+                        if (y < NWE) {
+                            al += x[2 * y][0];
+                            be += x[2 * y][1];
+                            ga += x[2 * y + 1][0];
+                        }
                 }
                 T cc, ss;
                 if (!jacobi_rot<T>(al, be, ga, tol2, atol2, cc, ss)) continue;
                 if (ga * ga > tol * (al * be)) big = 1;
+                rotated = 1;
+                if (!owner) continue;
                 LVT *gp = (LVT *)(G + p * ld + row0), *gq = (LVT *)(G + q * ld + row0);
                 LVT *vp = (LVT *)(V + p * ld + row0), *vq = (LVT *)(V + q * ld + row0);
                 if (cache && kk < 64) {
@@ -1132,10 +1166,9 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
                         }
                     }
                 }
-                rotated = 1;
             }
             // this wavefront's next partials read rows its own lanes just rotated
-            wave_fence_sync();
+            wave_order();
         }
         ++nsw;
         // every wavefront took the same decisions, so the vote needs no exchange.  Converged:
