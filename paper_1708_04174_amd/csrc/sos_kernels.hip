@@ -324,10 +324,30 @@ __device__ __forceinline__ float wave_allsum(float x) {
 
 // Sum over a group of GS consecutive lanes; every lane of the group gets the group's first
 // lane's result, so branches on it are uniform inside the group.
+// Cross-lane moves within rows of 16 lanes (DPP, no LDS round trip).
+enum { DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_ROW_MIRROR = 0x140, DPP_HALF_MIRROR = 0x141 };
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over an aligned group of GS (8, 16 or 32) lanes.  Each step adds a lane's partial sum
+// to its partner's, partners swapping roles; since a + b == b + a exactly, every lane of
+// the group ends with the bitwise-same total, so branches on it stay uniform in the group.
 template <int GS, typename T>
 __device__ __forceinline__ T group_allsum(T x) {
-    for (int off = GS / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, GS);
-    return __shfl(x, 0, GS);
+    x += dpp_mov<DPP_XOR1>(x);
+    x += dpp_mov<DPP_XOR2>(x);
+    x += dpp_mov<DPP_HALF_MIRROR>(x);
+    if constexpr (GS >= 16) x += dpp_mov<DPP_ROW_MIRROR>(x);
+    if constexpr (GS >= 32) x += __shfl_xor(x, 16, 64);
+    return x;
 }
 
 // Jacobi rotation for the column pair with squared norms al, be and inner product ga:
@@ -369,18 +389,22 @@ __device__ __forceinline__ bool jacobi_rot<double>(double al, double be, double 
 // lanes; makes g_p and g_q orthogonal.  Returns true if a rotation was applied.
 template <typename T, int GS, typename GP, typename VP>
 __device__ __forceinline__ bool os_rotate_pair(GP G, int ldg, VP V, int ldv, int N, int p, int q, T tol, T atol) {
-    constexpr int RPL = 8;          // rows per lane held in registers (N <= 8 GS); larger N: two passes
+    constexpr int RPL = 8;          // rows per lane held in registers (N <= 8 GS); larger N: streamed
     const int gl = threadIdx.x & (GS - 1);
     GP gp = G + (long long)p * ldg, gq = G + (long long)q * ldg;
     VP vp = V + (long long)p * ldv, vq = V + (long long)q * ldv;
     T al = 0, be = 0, ga = 0;
     if (N <= RPL * GS) {
-        T xp[RPL], xq[RPL];
+        // both columns of G and of V read up front: the V reads (global memory for the
+        // largest blocks) are in flight during the reduction and the rotation decision
+        T xp[RPL], xq[RPL], yp[RPL], yq[RPL];
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
             const int i = gl + GS * t;
             xp[t] = i < N ? gp[i] : (T)0;
             xq[t] = i < N ? gq[i] : (T)0;
+            yp[t] = i < N ? vp[i] : (T)0;
+            yq[t] = i < N ? vq[i] : (T)0;
         }
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
@@ -399,9 +423,8 @@ __device__ __forceinline__ bool os_rotate_pair(GP G, int ldg, VP V, int ldv, int
             if (i < N) {
                 gp[i] = cc * xp[t] - ss * xq[t];
                 gq[i] = ss * xp[t] + cc * xq[t];
-                const T a = vp[i], b = vq[i];
-                vp[i] = cc * a - ss * b;
-                vq[i] = ss * a + cc * b;
+                vp[i] = cc * yp[t] - ss * yq[t];
+                vq[i] = ss * yp[t] + cc * yq[t];
             }
         }
         return true;
