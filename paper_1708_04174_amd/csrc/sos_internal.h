@@ -92,6 +92,7 @@ struct RunParams {
     int gs_bucket[7];       // lanes per Jacobi column pair (8, 16 or 32) by block-size bucket:
                             // N < 32, < 64, < 96, < 128, < 192, < 256, >= 256
     int stall_checks;       // > 0: stop a problem that stopped improving (see the kernel) this many checks in a row
+    double jacobi_tol;      // relative coupling a Jacobi pair must exceed to be rotated (0: 16 eps of the type)
     unsigned long long *ts; // optional [start, end] wall-clock stamps of the launch (min / max over workgroups)
 };
 

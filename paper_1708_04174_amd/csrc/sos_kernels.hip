@@ -309,7 +309,12 @@ struct EigScratch {
     typename Lds<int>::type *s_flag;
     typename Lds<int>::type *s_sweeps;    // Jacobi sweeps run (diagnostic)
     double *s_red;
+    double jtol;                          // relative coupling a pair must exceed to rotate (0: 16 eps)
 };
+
+// Relative rotation threshold of the Jacobi sweeps: 16 eps of the type by default.
+template <typename T>
+__device__ __forceinline__ T jacobi_tol(double jtol) { return (T)(jtol > 0.0 ? jtol : 16.0 * TS<T>::eps); }
 
 // Wave sum with lane 0's result broadcast, so every lane holds the bitwise-same value
 // (a butterfly would leave lane-dependent rounding, and branches on it must not diverge).
@@ -349,6 +354,14 @@ __device__ __forceinline__ T group_allsum(T x) {
     if constexpr (GS >= 32) x += __shfl_xor(x, 16, 64);
     return x;
 }
+
+// Absolute floor of the coupling a pair must have to be rotated, in units of eps |W|_F
+// times the larger column norm.  Columns whose norms sit near the rounding level of W keep
+// picking up coupling of that size from every rotation of their partners (about eps |W|
+// times sqrt(N) accumulated over a sweep); a floor below that level makes them trade
+// rounding noise sweep after sweep.  Left unrotated, such a pair perturbs |W| by about
+// this floor, i.e. at the rounding level of W.
+__device__ __forceinline__ double jacobi_atol_factor(int N) { return 4.0 * sqrt((double)N); }
 
 // Jacobi rotation for the column pair with squared norms al, be and inner product ga:
 // rotate only while the pair is coupled beyond rounding, relative to both columns
@@ -529,8 +542,8 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
     // (16 eps) and absolutely (eps |W|_F times the larger column): below that, the pair's
     // contribution to |W| is under the rounding error of W itself, and columns of
     // near-zero eigenvalues stop trading noise
-    const T tol = (T)(16.0 * TS<T>::eps);
-    const T atol = (T)(TS<T>::eps * sqrt(fro2));
+    const T tol = jacobi_tol<T>(sc.jtol);
+    const T atol = (T)(jacobi_atol_factor(N) * TS<T>::eps * sqrt(fro2));
     const int M = N + (N & 1);
     const int H = M / 2;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
@@ -686,7 +699,7 @@ __device__ __forceinline__ void wave_fence_sync() {
 template <typename T>
 __device__ __noinline__ void project_block_wave(T *__restrict__ vs, T *__restrict__ us, int N, T *__restrict__ Vs, bool warm,
                                    typename Lds<T>::type *G, typename Lds<T>::type *V, int ld, T *__restrict__ Tm,
-                                   typename Lds<T>::type *sig, int *sweeps, int max_sweeps) {
+                                   typename Lds<T>::type *sig, int *sweeps, int max_sweeps, double jtol = 0.0) {
     typedef typename Lds<T>::type LT;
     const int lane = threadIdx.x & 63;
     if (N == 1) {
@@ -755,8 +768,8 @@ __device__ __noinline__ void project_block_wave(T *__restrict__ vs, T *__restric
     typedef typename V16<T>::v VT;
     typedef __attribute__((address_space(3))) VT LVT;
     const int nv = Np / V16<T>::n;   // 16-byte vectors per column, even
-    const T tol = (T)(16.0 * TS<T>::eps);
-    const T atol = (T)(TS<T>::eps * sqrt(fro2));
+    const T tol = jacobi_tol<T>(jtol);
+    const T atol = (T)(jacobi_atol_factor(N) * TS<T>::eps * sqrt(fro2));
     const T tol2 = tol * tol, atol2 = atol * atol;
     const int M = N + (N & 1);
     const int H = M / 2;
@@ -1019,8 +1032,8 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
         }
         __syncthreads();
     }
-    const T tol = (T)(16.0 * TS<T>::eps);
-    const T atol = (T)(TS<T>::eps * sqrt(fro2));
+    const T tol = jacobi_tol<T>(sc.jtol);
+    const T atol = (T)(jacobi_atol_factor(N) * TS<T>::eps * sqrt(fro2));
     const T tol2 = tol * tol, atol2 = atol * atol;
     const int M = N + (N & 1);
     const int H = M / 2;
@@ -1364,6 +1377,7 @@ __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
     sc.s_flag = as_lds<int>((void *)&s_flag);
     sc.s_sweeps = as_lds<int>((void *)&s_sweeps);
     sc.s_red = s_red;
+    sc.jtol = rp.jacobi_tol;
     if (rp.ts && threadIdx.x == 0) atomicMin(&rp.ts[0], (unsigned long long)wall_clock64());
 
     for (;;) {
@@ -1431,7 +1445,7 @@ __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
                             project_block_wave<T>(v + off, u + off, N, rp.warm_eig ? vstore + vo : nullptr,
                                                   rp.warm_eig && warm, G, G + (long long)N * ldp, ldp,
                                                   Tm + (long long)li * P.nmax * P.nmax, G + 2LL * N * ldp, &s_sweeps,
-                                                  rp.max_sweeps);
+                                                  rp.max_sweeps, rp.jacobi_tol);
                         }
                         ++li;
                         loff += lpj_region(N, (int)sizeof(T));
@@ -1461,7 +1475,7 @@ __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
                         const int ldp = lpj_ld(N, (int)sizeof(T));
                         project_block_wave<T>(v + off, u + off, N, rp.warm_eig ? vstore + voff : nullptr,
                                               rp.warm_eig && warm, s_mat, s_mat + (long long)N * ldp, ldp, Tm, s_sig,
-                                              &s_sweeps, rp.max_sweeps);
+                                              &s_sweeps, rp.max_sweeps, rp.jacobi_tol);
                     }
                     __syncthreads();
                     voff += (long long)N * N;
@@ -1586,6 +1600,7 @@ __global__ __launch_bounds__(NT) void warm_start_kernel(RunParams rp, const floa
     sc.s_flag = as_lds<int>((void *)&s_flag);
     sc.s_sweeps = as_lds<int>((void *)&s_sweeps);
     sc.s_red = s_red;
+    sc.jtol = 0.0;
     for (int p = blockIdx.x; p < rp.count; p += gridDim.x) {
     const ProbDesc &P = rp.probs[p];
     T *u = TS<T>::u(P);
