@@ -3,10 +3,10 @@
 Times fixed-length batched runs (the same persistent kernel the solve uses, stopped after
 a fixed number of iterations) and picks
   1. per block-size bucket (N < 32, 64, 96, 128, 192, 256, larger): the lanes that
-     share one Jacobi column pair (8, 16 or 32) in the group form of the eigensolver
-     (blocks too large for the LDS forms);
+     share one Jacobi column pair (8, 16 or 32) in the lane-group form of the
+     eigensolver (blocks too large for the LDS form);
   2. for the whole batch: the eigensolver form for blocks that fit in LDS (rows split
-     over the wavefronts, or one wavefront per block), threads per workgroup and
+     over the wavefronts, or lane groups throughout), threads per workgroup and
      resident workgroups per CU (which also sets the LDS each workgroup may use).
 Writes the schedule JSON that sos_batch_setup reads.
 
@@ -74,7 +74,7 @@ def tune(probs, precision: int, iters: int = 40, sample: int = 64, log=print) ->
     pick = rng.choice(len(probs), size=min(len(probs), 4 * sample), replace=False)
     works = [B.setup_problem(probs[i], st) for i in pick]
     res = {}
-    for ew in (2, 1):
+    for ew in (2, 0):
         for thr in (256, 512):
             for wpc in (1, 2):
                 s = dict(sched)

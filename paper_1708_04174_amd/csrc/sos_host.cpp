@@ -858,6 +858,8 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         B->use_graph = json_num(schedule_json, "use_graph", 1) != 0.0;
         B->warm_eig = (int)json_num(schedule_json, "warm_eig", 1);
         B->eig_wave = (int)json_num(schedule_json, "eig_wave", 2);
+        if (B->eig_wave != 0 && B->eig_wave != 2)
+            throw Status(SOS_E_INVAL, "schedule eig_wave must be 0 (lane groups) or 2 (rows over wavefronts)");
         // LDS per workgroup: what wg_per_cu resident workgroups can share (160 KiB per CU, less
         // about 10 KiB of static LDS each), unless the schedule says otherwise
         const double lds_share = std::min<double>(kLdsBudget, 163840.0 / B->wg_per_cu - 1024.0);

@@ -83,8 +83,9 @@ struct RunParams {
     int max_sweeps;
     int warm_eig;           // start each block's Jacobi sweeps from the previous iteration's eigenvectors
     int lds_budget;         // dynamic LDS bytes the launch may use
-    int eig_wave;           // blocks that fit in LDS: 1 one-wavefront eigensolver, 2 rows split over wavefronts
-    int lds_mat_off, lds_nmax, lds_nmax_g, lpj_nmax;   // filled in by the launcher
+    int eig_wave;           // 2: blocks that fit in LDS use the rows-over-wavefronts eigensolver;
+                            // 0: every block uses the lane-group form
+    int lds_mat_off, lds_nmax, lds_nmax_g, rows_nmax;   // filled in by the launcher
     int accumulate;         // 0: out[TOTAL] = iterations of this launch; 1: out[TOTAL] += them, and the
                             //    iteration budget is iters + out[WARM] - out[TOTAL] (at least min_iters)
     int warm_budget;        // > 0 (first launch of a solve): restart a warm start (tk[3] = 1) from the cold

@@ -646,26 +646,7 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
     __syncthreads();
 }
 
-// ----------------------------------------------------------------------------- PSD projection, one wavefront
-// Leading dimension for a column-major N x N matrix in LDS that one wavefront walks lane
-// per column with 16-byte reads: rows are padded with zeros to a whole number of 32-byte
-// chunks (kLpjChunk elements) and ld = 4 dwords (mod 32 banks), so lanes reading the same
-// chunk of columns p and p' with p != p' (mod 8) hit distinct 4-bank groups.
-__host__ __device__ __forceinline__ int lpj_rows(int N, int elem_bytes) {
-    const int c = 32 / elem_bytes;
-    return (N + c - 1) / c * c;
-}
-__host__ __device__ __forceinline__ int lpj_ld(int N, int elem_bytes) {
-    const int q = 128 / elem_bytes, r = 16 / elem_bytes;
-    const int np = lpj_rows(N, elem_bytes);
-    return q * ((np - r + q - 1) / q) + r;
-}
-
-// LDS footprint (elements) of one block in the one-wavefront solver: G, V, then sigma
-__host__ __device__ __forceinline__ int lpj_region(int N, int elem_bytes) {
-    return 2 * N * lpj_ld(N, elem_bytes) + ((N + 3) & ~3);
-}
-
+// ----------------------------------------------------------------------------- PSD projection, helpers
 // 16-byte vector of T, in LDS
 template <typename T> struct V16;
 template <> struct V16<float> {
@@ -684,220 +665,6 @@ template <> __device__ __forceinline__ double hsum<double>(V16<double>::v x) { r
 // operations are performed in issue order, so a read issued after a write (by any lane of
 // the same wavefront) returns the written value without waiting for the write to finish.
 __device__ __forceinline__ void wave_order() { __builtin_amdgcn_wave_barrier(); }
-
-__device__ __forceinline__ void wave_fence_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// Same projection as project_block, run by ONE wavefront: one lane owns one column pair
-// per round (several for N > 128), computes the three inner products serially and
-// rotates its two columns of G and V.  No workgroup barrier and no cross-lane reduction
-// inside the sweeps: lanes only share LDS, ordered by wavefront fences between rounds.
-// G, V: column-major in LDS with leading dimension ld = lpj_ld(N); Tm: N x N global temp.
-template <typename T>
-__device__ __noinline__ void project_block_wave(T *__restrict__ vs, T *__restrict__ us, int N, T *__restrict__ Vs, bool warm,
-                                   typename Lds<T>::type *G, typename Lds<T>::type *V, int ld, T *__restrict__ Tm,
-                                   typename Lds<T>::type *sig, int *sweeps, int max_sweeps, double jtol = 0.0) {
-    typedef typename Lds<T>::type LT;
-    const int lane = threadIdx.x & 63;
-    if (N == 1) {
-        if (lane == 0) {
-            const T w = vs[0];
-            const T x = w > (T)0 ? w : (T)0;
-            us[0] = x;
-            vs[0] = x - w;
-            if (Vs) Vs[0] = (T)1;
-        }
-        wave_fence_sync();
-        return;
-    }
-    double fro2 = 0.0;
-    for (int idx = lane; idx < N * N; idx += 64) {
-        const int j = idx / N, i = idx - (idx / N) * N;
-        const int a = i > j ? i : j, bb = i > j ? j : i;
-        const T x = vs[svec_idx(a, bb, N)];
-        fro2 += (double)x * (double)x;
-        if (warm) {
-            Tm[j * N + i] = x;
-            V[j * ld + i] = Vs[j * N + i];
-        } else {
-            G[j * ld + i] = x;
-            V[j * ld + i] = (i == j) ? (T)1 : (T)0;
-        }
-    }
-    const int Np = lpj_rows(N, (int)sizeof(T));
-    for (int idx = lane; idx < (Np - N) * N; idx += 64) {
-        const int j = idx / (Np - N), i = N + idx - (idx / (Np - N)) * (Np - N);
-        G[j * ld + i] = (T)0;
-        V[j * ld + i] = (T)0;
-    }
-    fro2 = wave_allsum(fro2);
-    wave_fence_sync();
-    if (warm) {
-        // G = W V_prev, a 4 x 4 tile per lane
-        const int nt = (N + 3) >> 2;
-        for (int t = lane; t < nt * nt; t += 64) {
-            const int i0 = (t / nt) * 4, j0 = (t - (t / nt) * nt) * 4;
-            T acc[4][4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
-#pragma unroll 4
-            for (int kk = 0; kk < N; ++kk) {
-                T wa[4], vb[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) wa[a] = (i0 + a < N) ? Tm[kk * N + i0 + a] : (T)0;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) vb[b] = (j0 + b < N) ? V[(j0 + b) * ld + kk] : (T)0;
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[a][b] += wa[a] * vb[b];
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    if (i0 + a < N && j0 + b < N) G[(j0 + b) * ld + i0 + a] = acc[a][b];
-        }
-        wave_fence_sync();
-    }
-    typedef typename V16<T>::v VT;
-    typedef __attribute__((address_space(3))) VT LVT;
-    const int nv = Np / V16<T>::n;   // 16-byte vectors per column, even
-    const T tol = jacobi_tol<T>(jtol);
-    const T atol = (T)(jacobi_atol_factor(N) * TS<T>::eps * sqrt(fro2));
-    const T tol2 = tol * tol, atol2 = atol * atol;
-    const int M = N + (N & 1);
-    const int H = M / 2;
-    int nsw = 0;
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        int rotated = 0, big = 0;   // big: some rotation of the sweep had coupling above sqrt(tol)
-        for (int r = 0; r < M - 1; ++r) {
-            for (int kk = lane; kk < H; kk += 64) {
-                // round-robin pair without ordering p < q (the rotation does not need it):
-                // lanes kk, kk+1, ... then touch consecutive columns r+kk and r-kk, whose
-                // 16-byte chunks fall in distinct bank groups
-                int p, q;
-                if (kk == 0) {
-                    p = r;
-                    q = M - 1;
-                } else {
-                    p = r + kk;
-                    if (p >= M - 1) p -= M - 1;
-                    q = r - kk;
-                    if (q < 0) q += M - 1;
-                }
-                if (p >= N || q >= N) continue;
-                // columns p, q of G and V in 32-byte chunks (two 16-byte vectors per column);
-                // rows N..Np-1 are zero, so whole chunks need no tail
-                LVT *gp = (LVT *)(G + p * ld), *gq = (LVT *)(G + q * ld);
-                VT sa = (VT)(T)0, sb = (VT)(T)0, sg = (VT)(T)0;
-#pragma unroll 2
-                for (int c = 0; c < nv; c += 2) {
-                    const VT a0 = gp[c], a1 = gp[c + 1], b0 = gq[c], b1 = gq[c + 1];
-                    sa += a0 * a0 + a1 * a1;
-                    sb += b0 * b0 + b1 * b1;
-                    sg += a0 * b0 + a1 * b1;
-                }
-                const T al = hsum<T>(sa), be = hsum<T>(sb), ga = hsum<T>(sg);
-                T cc, ss;
-                if (!jacobi_rot<T>(al, be, ga, tol2, atol2, cc, ss)) continue;
-                if (ga * ga > tol * (al * be)) big = 1;
-                LVT *vp = (LVT *)(V + p * ld), *vq = (LVT *)(V + q * ld);
-                // software pipelined: the next chunk is read before the current one is written
-                // (columns p and q are distinct, so the two never overlap)
-                VT A0 = gp[0], A1 = gp[1], B0 = gq[0], B1 = gq[1];
-                VT C0 = vp[0], C1 = vp[1], D0 = vq[0], D1 = vq[1];
-                for (int c = 0; c < nv; c += 2) {
-                    VT nA0, nA1, nB0, nB1, nC0, nC1, nD0, nD1;
-                    const bool more = c + 2 < nv;
-                    if (more) {
-                        nA0 = gp[c + 2]; nA1 = gp[c + 3]; nB0 = gq[c + 2]; nB1 = gq[c + 3];
-                        nC0 = vp[c + 2]; nC1 = vp[c + 3]; nD0 = vq[c + 2]; nD1 = vq[c + 3];
-                    }
-                    gp[c] = cc * A0 - ss * B0;
-                    gp[c + 1] = cc * A1 - ss * B1;
-                    gq[c] = ss * A0 + cc * B0;
-                    gq[c + 1] = ss * A1 + cc * B1;
-                    vp[c] = cc * C0 - ss * D0;
-                    vp[c + 1] = cc * C1 - ss * D1;
-                    vq[c] = ss * C0 + cc * D0;
-                    vq[c + 1] = ss * C1 + cc * D1;
-                    if (more) {
-                        A0 = nA0; A1 = nA1; B0 = nB0; B1 = nB1;
-                        C0 = nC0; C1 = nC1; D0 = nD0; D1 = nD1;
-                    }
-                }
-                rotated = 1;
-            }
-            wave_fence_sync();
-        }
-        ++nsw;
-        // converged: no rotation, or every rotation of the sweep was small (relative
-        // coupling <= sqrt(tol)); cyclic Jacobi converges quadratically, so what such a
-        // sweep leaves is coupling of order tol, which the next sweep would not rotate
-        if (!__any(rotated) || !__any(big)) break;
-    }
-    if (lane == 0) atomicAdd(sweeps, nsw);
-    for (int j = lane; j < N; j += 64) {
-        T s = 0;
-        const LT *gj = G + j * ld;
-        for (int i = 0; i < N; ++i) s += gj[i] * gj[i];
-        sig[j] = sqrt(s);
-    }
-    wave_fence_sync();
-    // u = lower((W + V Sigma V^T) / 2), v = u - w, 4 x 4 tiles on and below the diagonal
-    const int nt = (N + 3) >> 2;
-    const int ntri = nt * (nt + 1) / 2;
-    for (int t = lane; t < ntri; t += 64) {
-        int ta = 0, rem = t;
-        while (rem > ta) {
-            rem -= ta + 1;
-            ++ta;
-        }
-        const int a0 = ta * 4, b0 = rem * 4;
-        T acc[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
-        for (int j = 0; j < N; ++j) {
-            const T sg = sig[j];
-            T va[4], vb[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) va[a] = (a0 + a < N) ? V[j * ld + a0 + a] * sg : (T)0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) vb[b] = (b0 + b < N) ? V[j * ld + b0 + b] : (T)0;
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] += va[a] * vb[b];
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int i = a0 + a, j = b0 + b;
-                if (i < N && j <= i) {
-                    const int s = svec_idx(i, j, N);
-                    const T w = vs[s];
-                    const T x = (T)0.5 * (w + acc[a][b]);
-                    us[s] = x;
-                    vs[s] = x - w;
-                }
-            }
-    }
-    if (Vs)
-        for (int idx = lane; idx < N * N; idx += 64) {
-            const int j = idx / N, i = idx - (idx / N) * N;
-            Vs[j * N + i] = V[j * ld + i];
-        }
-    wave_fence_sync();
-}
 
 // ----------------------------------------------------------------------------- PSD projection, rows per wavefront
 // Same projection again, with the rows of the column-major N x N matrices G and V split
@@ -1413,71 +1180,19 @@ __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
         bool was_cert = false;
         int since_best = 0;
         bool stalled = false;
-        // blocks small enough for the one-wavefront solver run side by side, one wavefront
-        // each, when there are two or three of them and their G, V, sigma fit in LDS together
-        int nl = 0;
-        long long lbytes = 0;
-        for (int bk = 0; bk < P.nblk; ++bk)
-            if (P.blk_N[bk] <= rp.lpj_nmax) {
-                ++nl;
-                lbytes += (long long)lpj_region(P.blk_N[bk], (int)sizeof(T)) * (long long)sizeof(T);
-            }
-        const bool side = rp.eig_wave == 1 && nl >= 2 && nl <= 3 && nl <= NT / 64 &&
-                          rp.lds_mat_off + lbytes <= rp.lds_budget;
         while (it < cap) {
             t0 = wall_clock64();
             affine_phase<T, NT, T>(P, rp, wy, wx, s_z, s_red);
             const unsigned long long t1 = wall_clock64();
             t_aff += t1 - t0;
-            if (side) {
-                // one wavefront per block, each with its own G, V, sigma in LDS and its own
-                // slice of the global temporary
-                const int w = threadIdx.x >> 6;
-                int li = 0;
-                long long loff = 0, vo = 0;
-                for (int bk = 0; bk < P.nblk; ++bk) {
-                    const int N = P.blk_N[bk];
-                    if (N <= rp.lpj_nmax) {
-                        if (w == li) {
-                            const int off = P.blk_off[bk];
-                            const int ldp = lpj_ld(N, (int)sizeof(T));
-                            typename Lds<T>::type *G = s_mat + loff;
-                            project_block_wave<T>(v + off, u + off, N, rp.warm_eig ? vstore + vo : nullptr,
-                                                  rp.warm_eig && warm, G, G + (long long)N * ldp, ldp,
-                                                  Tm + (long long)li * P.nmax * P.nmax, G + 2LL * N * ldp, &s_sweeps,
-                                                  rp.max_sweeps, rp.jacobi_tol);
-                        }
-                        ++li;
-                        loff += lpj_region(N, (int)sizeof(T));
-                    }
-                    vo += (long long)N * N;
-                }
-                __syncthreads();
-            }
             long long voff = 0;
             for (int bk = 0; bk < P.nblk; ++bk) {
                 const int off = P.blk_off[bk];
                 const int N = P.blk_N[bk];
-                if (N <= rp.lpj_nmax) {
-                    if (side) {
-                        voff += (long long)N * N;
-                        continue;
-                    }
-                    if (rp.eig_wave == 2) {
-                        // rows split over the wavefronts, G, V and partial sums in LDS
-                        project_block_rows<T, NT>(v + off, u + off, N, rp.warm_eig ? vstore + voff : nullptr,
-                                                  rp.warm_eig && warm, s_mat, Tm, sc, rp.max_sweeps);
-                        voff += (long long)N * N;
-                        continue;
-                    }
-                    // one wavefront, lane per column pair, G and V in LDS
-                    if ((threadIdx.x >> 6) == 0) {
-                        const int ldp = lpj_ld(N, (int)sizeof(T));
-                        project_block_wave<T>(v + off, u + off, N, rp.warm_eig ? vstore + voff : nullptr,
-                                              rp.warm_eig && warm, s_mat, s_mat + (long long)N * ldp, ldp, Tm, s_sig,
-                                              &s_sweeps, rp.max_sweeps, rp.jacobi_tol);
-                    }
-                    __syncthreads();
+                if (N <= rp.rows_nmax) {
+                    // rows split over the wavefronts, G, V and partial sums in LDS
+                    project_block_rows<T, NT>(v + off, u + off, N, rp.warm_eig ? vstore + voff : nullptr,
+                                              rp.warm_eig && warm, s_mat, Tm, sc, rp.max_sweeps);
                     voff += (long long)N * N;
                     continue;
                 }
@@ -1629,15 +1344,8 @@ __global__ __launch_bounds__(NT) void warm_start_kernel(RunParams rp, const floa
         T *g1 = Tm + (long long)P.nmax * P.nmax, *g2 = g1 + (long long)P.nmax * P.nmax;
         for (int pass = 0; pass < 2; ++pass) {
             T *blk = (pass == 0 ? u : v) + off;   // projected in place via the scratch wx
-            if (N <= rp.lpj_nmax && rp.eig_wave == 2) {
+            if (N <= rp.rows_nmax) {
                 project_block_rows<T, NT>(blk, wx, N, nullptr, false, s_mat, Tm, sc, rp.max_sweeps);
-            } else if (N <= rp.lpj_nmax) {
-                if ((threadIdx.x >> 6) == 0) {
-                    const int ldp = lpj_ld(N, (int)sizeof(T));
-                    project_block_wave<T>(blk, wx, N, nullptr, false, s_mat, s_mat + (long long)N * ldp, ldp, Tm, s_sig,
-                                          &s_sweeps, rp.max_sweeps);
-                }
-                __syncthreads();
             } else if (N <= rp.lds_nmax) {
                 project_block<T, NT>(blk, wx, N, nullptr, false, s_mat, s_mat + (long long)N * N, N, Tm, s_sig, sc,
                                      rp.max_sweeps, lanes_per_pair(rp, N));
@@ -1730,7 +1438,7 @@ __global__ void reset_state(const ProbDesc *probs, int count) {
 // lds_nmax, or G alone for blocks up to lds_nmax_g; larger blocks work in global scratch.
 template <typename T>
 void lds_layout(int eig_ld, int lds_budget, int nw, int &mat_off, int &lds_nmax, int &lds_nmax_g, size_t &bytes,
-                int use_lpj, int &lpj_nmax) {
+                int eig_wave, int &rows_nmax) {
     size_t off = sizeof(T) * (size_t)(eig_ld + 1);
     off = (off + 15) & ~(size_t)15;
     mat_off = (int)off;
@@ -1743,24 +1451,18 @@ void lds_layout(int eig_ld, int lds_budget, int nw, int &mat_off, int &lds_nmax,
     const size_t need1 = lds_nmax_g ? off + sizeof(T) * (size_t)lds_nmax_g * lds_nmax_g : off;
     bytes = need2 > need1 ? need2 : need1;
     // one-wavefront form: G and V with the padded leading dimension
-    // one-wavefront form (use_lpj 1) or rows-per-wavefront form (use_lpj 2)
-    lpj_nmax = 0;
+    // rows-per-wavefront form (eig_wave 2): G, V, partial records and sigma of one block
+    rows_nmax = 0;
     size_t need3 = off;
-    if (use_lpj == 1) {
-        for (int N = eig_ld; N >= 1 && !lpj_nmax; --N)
-            if ((long long)(off + sizeof(T) * 2 * (size_t)N * lpj_ld(N, (int)sizeof(T))) <= lds_budget) lpj_nmax = N;
-        if (lpj_nmax) need3 = off + sizeof(T) * 2 * (size_t)lpj_nmax * lpj_ld(lpj_nmax, (int)sizeof(T));
-    } else if (use_lpj == 2) {
-        for (int N = eig_ld; N >= 1 && !lpj_nmax; --N)
-            if ((long long)(off + sizeof(T) * (size_t)rows_region(N, (int)sizeof(T), nw)) <= lds_budget) lpj_nmax = N;
-        if (lpj_nmax) need3 = off + sizeof(T) * (size_t)rows_region(lpj_nmax, (int)sizeof(T), nw);
+    if (eig_wave == 2) {
+        for (int N = eig_ld; N >= 1 && !rows_nmax; --N)
+            if ((long long)(off + sizeof(T) * (size_t)rows_region(N, (int)sizeof(T), nw)) <= lds_budget) rows_nmax = N;
+        if (rows_nmax) need3 = off + sizeof(T) * (size_t)rows_region(rows_nmax, (int)sizeof(T), nw);
     }
     if (need3 > bytes) bytes = need3;
     // the affine step's k-vector and partial sums alias the eigen region
     const size_t need_z = off + sizeof(double) * 2 * SOS_KMAX_LDS;
     if (need_z > bytes) bytes = need_z;
-    // blocks side by side may use the whole budget
-    if (use_lpj == 1 && lpj_nmax && (size_t)lds_budget > bytes) bytes = (size_t)lds_budget;
 }
 
 template <typename T, int NT>
@@ -1768,7 +1470,7 @@ int launch_t(int grid, const RunParams &rp_in, hipStream_t st) {
     RunParams rp = rp_in;
     size_t lds = 0;
     lds_layout<T>(rp.eig_ld, rp.lds_budget, NT / 64, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds, rp.eig_wave,
-                  rp.lpj_nmax);
+                  rp.rows_nmax);
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&admm_persistent<T, NT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1842,7 +1544,7 @@ int sos_launch_warm_start(int fp64, int threads, int grid, const RunParams &rp_i
     {                                                                                                           \
         lds_layout<TT>(rp.eig_ld, rp.lds_budget, NTT / 64, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds,      \
                        rp.eig_wave,                                                                             \
-                       rp.lpj_nmax);                                                                            \
+                       rp.rows_nmax);                                                                            \
         if (lds > 64 * 1024) {                                                                                  \
             (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&warm_start_kernel<TT, NTT>),               \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                    \

@@ -226,3 +226,50 @@ def test_single_mixed_precision_solve(B):
           f"gamma {x[0]:.6f} vs {r.x[0]:.6f}", flush=True)
     assert inf["status"] == B.SOS_SOLVED and inf["polish_iters"] >= 1
     assert abs(x[0] - r.x[0]) <= 5e-4 * max(1.0, abs(r.x[0]))
+
+
+@pytest.mark.parametrize("sched", ['{"eig_wave": 2}', '{"eig_wave": 0, "gs_n32": 8, "gs_n64": 32}',
+                                   '{"eig_wave": 0, "gs_n32": 16, "gs_n64": 8}',
+                                   '{"eig_wave": 2, "block_threads": 256, "wg_per_cu": 2}'])
+def test_batch_eigensolver_forms_match_the_oracle(B, sched):
+    # every eigensolver form a schedule can pick (rows over the wavefronts, lane groups
+    # of 8, 16 or 32 per column pair) gives the oracle's gamma and status (FP64)
+    probs = [F.pop_unconstrained(n, sd) for n, sd in ((4, 0), (5, 1), (6, 2))] + [F.pop_ball(3, 1)]
+    s = B.sos_default_settings(tol=1e-6, max_iters=4000)
+    works = [B.setup_problem(p, s) for p in probs]
+    bt = B.sos_batch_setup(works, sched)
+    infos = B.sos_batch_solve(bt)
+    for p, inf, w in zip(probs, infos, works):
+        r = Oracle.from_problem(p).solve(tol=1e-6, max_iters=4000)
+        x, _, _ = B.sos_get_solution(w)
+        err = abs(x[0] - r.x[0]) / max(1.0, abs(r.x[0]))
+        print(f"[forms] {sched} N={p.psd_dims} {inf['status_name']} iters {inf['iters']} (oracle {r.iters}) "
+              f"gamma err {err:.1e}", flush=True)
+        assert inf["status"] == r.status and err <= 1e-6
+    bt.free()
+
+
+def test_autotuner_writes_a_schedule_the_batch_accepts(B):
+    import json
+
+    from paper_1708_04174_amd import autotune
+    probs = [F.pop_unconstrained(n, sd) for n, sd in ((4, 0), (5, 1), (6, 2), (7, 3))]
+    sched = autotune.tune(probs, B.SOS_FP32_MIXED, iters=10, sample=4, log=lambda m: print(m, flush=True))
+    for k in ("block_threads", "wg_per_cu", "eig_wave", "gs_n32", "use_graph"):
+        assert k in sched
+    # the tuned schedule changes speed, not answers: statuses as with the default schedule,
+    # gamma within the mixed-precision bound
+    st = B.sos_default_settings(tol=1e-4, precision=B.SOS_FP32_MIXED)
+    out = []
+    for sc in (None, json.dumps(sched)):
+        works = [B.setup_problem(p, st) for p in probs]
+        bt = B.sos_batch_setup(works, sc)
+        infos = B.sos_batch_solve(bt)
+        gam = [B.sos_get_solution(w)[0][0] if i["status"] == B.SOS_SOLVED else None for i, w in zip(infos, works)]
+        out.append(([i["status"] for i in infos], gam))
+        bt.free()
+    print(f"[tune] statuses default {out[0][0]} tuned {out[1][0]}", flush=True)
+    assert out[0][0] == out[1][0]
+    for a, b in zip(out[0][1], out[1][1]):
+        if a is not None:
+            assert abs(a - b) <= 5e-4 * max(1.0, abs(a))
