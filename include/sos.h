@@ -170,8 +170,12 @@ void sos_free(sos_work *w);
 /* Groups `count` handles (same precision) for one persistent launch: workgroups
    pull problems from a device queue ordered by decreasing cost.  schedule_json
    (may be NULL) holds the tuned launch shape, e.g.
-   {"block_threads": 256, "wg_per_cu": 2, "max_sweeps": 60, "use_graph": 1}.
-   The handles must outlive the batch. */
+   {"block_threads": 512, "wg_per_cu": 1, "max_sweeps": 60, "use_graph": 1, "eig_wave": 2}.
+   Keys: block_threads, wg_per_cu, max_sweeps, warm_eig (Jacobi warm start from the last
+   eigenvectors), use_graph (capture the launches in a hipGraph), eig_wave (2: rows form
+   for blocks that fit in LDS, 0: lane-group form for all), lds_kb, gs_n32 .. gs_big (lanes
+   per column pair of the lane-group form by block size), one_launch (mixed form: 1 runs
+   both phases in one launch, 0 in two).  The handles must outlive the batch. */
 int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_json,
                     sos_batch **out);
 
@@ -188,10 +192,11 @@ int sos_batch_reset(sos_batch *b);
    batch's stream around it). */
 double sos_batch_last_ms(const sos_batch *b);
 
-/* Device time in ms of one kernel of the last sos_batch_solve, from hip events
-   recorded right around it: phase 0 = the persistent solve kernel (FP32 in the
-   mixed form), phase 1 = the FP64 polish kernel (0 for an FP64 batch).  Returns a
-   negative value if unavailable. */
+/* Device time in ms of one kernel of the last sos_batch_solve, from device wall-clock
+   stamps the kernel writes (first workgroup start to last workgroup end): phase 0 = the
+   persistent solve kernel (the FP32 kernel of the two-launch mixed form, or the single
+   launch that runs both phases of the mixed form), phase 1 = the FP64 kernel of the
+   two-launch mixed form (0 otherwise).  Returns a negative value if unavailable. */
 double sos_batch_phase_ms(const sos_batch *b, int32_t phase);
 
 void sos_batch_free(sos_batch *b);

@@ -120,6 +120,8 @@ struct sos_batch {
     double last_ms = 0.0, phase_ms[2] = {0.0, 0.0};
     bool use_graph = true;
     int warm_eig = 1, lds_budget = 0, eig_wave = 2;
+    int one_launch = 1;   // mixed form: both phases in one launch (threads 256 or 512)
+    bool used_one_launch = false;
     int gs_bucket[7] = {16, 16, 16, 16, 16, 16, 16};
     sos_settings st{};
 };
@@ -858,6 +860,7 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         B->use_graph = json_num(schedule_json, "use_graph", 1) != 0.0;
         B->warm_eig = (int)json_num(schedule_json, "warm_eig", 1);
         B->eig_wave = (int)json_num(schedule_json, "eig_wave", 2);
+        B->one_launch = (int)json_num(schedule_json, "one_launch", 1);
         if (B->eig_wave != 0 && B->eig_wave != 2)
             throw Status(SOS_E_INVAL, "schedule eig_wave must be 0 (lane groups) or 2 (rows over wavefronts)");
         // LDS per workgroup: what wg_per_cu resident workgroups can share (160 KiB per CU, less
@@ -962,12 +965,23 @@ static void enqueue_batch(sos_batch *B) {
         rp.stall_checks = kStallChecks;
         rp.warm_budget = B->st.warm_budget;
         rp.ts = B->d_ts;
+        RunParams rp2 = batch_params(B, RUN_SOLVE, B->st.max_iters, B->st.polish_iters, B->st.tol);
+        rp2.accumulate = 1;
+        if (B->one_launch) {
+            // both phases in one launch: each problem goes on to FP64 as soon as its own
+            // FP32 phase ends
+            const int rc = sos_launch_admm_mixed(B->threads, B->grid, rp, rp2, B->stream);
+            if (rc == 0) {
+                B->used_one_launch = true;
+                return;
+            }
+            if (rc != -1) throw Status(SOS_E_HIP, "launch failed");
+        }
+        B->used_one_launch = false;
         if (sos_launch_admm(0, B->threads, B->grid, rp, B->stream)) throw Status(SOS_E_HIP, "launch failed");
         if (sos_launch_cast_state(B->d_desc, nullptr, B->count, 1, B->stream, B->max_len))
             throw Status(SOS_E_HIP, "cast launch failed");
         if (sos_launch_reset(B->d_counter, B->stream, B->d_ts + 2)) throw Status(SOS_E_HIP, "reset launch failed");
-        RunParams rp2 = batch_params(B, RUN_SOLVE, B->st.max_iters, B->st.polish_iters, B->st.tol);
-        rp2.accumulate = 1;
         rp2.ts = B->d_ts + 2;
         if (sos_launch_admm(1, B->threads, B->grid, rp2, B->stream)) throw Status(SOS_E_HIP, "launch failed");
     }
@@ -1009,7 +1023,7 @@ int sos_batch_solve(sos_batch *B, sos_info *infos) {
         hip_check(hipMemcpy(ts, B->d_ts, sizeof(ts), hipMemcpyDeviceToHost), "copy");
         const double khz = wall_clock_khz();
         B->phase_ms[0] = ts[1] > ts[0] ? (double)(ts[1] - ts[0]) / khz : -1.0;
-        B->phase_ms[1] = B->fp64 ? 0.0 : (ts[3] > ts[2] ? (double)(ts[3] - ts[2]) / khz : -1.0);
+        B->phase_ms[1] = (B->fp64 || B->used_one_launch) ? 0.0 : (ts[3] > ts[2] ? (double)(ts[3] - ts[2]) / khz : -1.0);
         for (int i = 0; i < B->count; ++i) {
             sos_work *w = B->probs[i];
             w->active64 = true;

@@ -99,6 +99,9 @@ struct RunParams {
 
 // host-side launchers implemented in sos_kernels.hip
 int sos_launch_admm(int fp64, int threads, int grid, const RunParams &rp, void *stream);
+// the mixed form in one launch (FP32 phase, widening, FP64 phase per problem); threads 256 or
+// 512, else returns -1 and the caller launches the phases separately
+int sos_launch_admm_mixed(int threads, int grid, const RunParams &rp32, const RunParams &rp64, void *stream);
 int sos_launch_reset(int *counter, void *stream, unsigned long long *ts = nullptr);
 int sos_launch_cast_state(const ProbDesc *probs_dev, const int *ids, int count, int to64, void *stream,
                           int max_len);

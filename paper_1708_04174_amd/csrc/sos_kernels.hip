@@ -1123,6 +1123,157 @@ __device__ __noinline__ int residual_phase(const ProbDesc &P, double tol, double
 // launch bounds: at least 2 waves per SIMD (the second argument is waves per execution
 // unit), i.e. at most 256 VGPRs, so that two or more workgroups (problems) can share a CU
 // and hide each other's latency
+// One solve phase of one problem (RUN_STEP: exactly rp.iters iterations; RUN_SOLVE: to tol,
+// a certificate, the budget, or a stall) by the whole workgroup, in precision T.  Returns
+// the status the phase ended with (0: stalled or out of budget).
+template <typename T, int NT>
+__device__ __noinline__ int run_phase(const ProbDesc &P, const RunParams &rp, char *wbase, char *ebase, char *dyn_lds,
+                                      const EigScratch &sc) {
+    // dynamic LDS: sigma (eig_ld values), then the eigensolver's matrices (layout by the
+    // launcher for this T); the affine step's k-vector and the small solve's partial sums
+    // share the eigen region, the two phases being separated by barriers
+    typename Lds<T>::type *s_sig = as_lds<T>(dyn_lds);
+    typename Lds<T>::type *s_mat = as_lds<T>(dyn_lds + rp.lds_mat_off);
+    double *s_z = reinterpret_cast<double *>(dyn_lds + rp.lds_mat_off);
+    double *s_red = sc.s_red;
+    T *wy = reinterpret_cast<T *>(wbase);
+    T *wx = wy + ((P.m + 63) & ~63);
+    T *Tm = reinterpret_cast<T *>(ebase);
+    T *u = TS<T>::u(P);
+    T *v = TS<T>::v(P);
+    T *vstore = TS<T>::vstore(P);
+    bool warm = P.tk[2] != 0.0;
+    if (threadIdx.x == 0) *sc.s_sweeps = 0;
+
+    int it = 0;
+    int status = 0;
+    unsigned long long t_aff = 0, t_eig = 0, t_res = 0, t0 = 0;   // wall-clock ticks by phase
+    // iteration budget: in an accumulating (second) phase, what the first phase left over
+    int cap = rp.iters;
+    if (rp.accumulate) {
+        cap = rp.iters + (int)P.out[SOS_OUT_WARM] - (int)P.out[SOS_OUT_TOTAL];
+        if (cap < rp.min_iters) cap = rp.min_iters;
+    }
+    // a warm start under judgement (first launch of a solve only)
+    bool trying = rp.mode == RUN_SOLVE && !rp.accumulate && rp.warm_budget > 0 && P.tk[3] != 0.0;
+    int it_warm = 0;   // iterations of an abandoned warm attempt
+    double best = INFINITY, best_ce = INFINITY;
+    bool was_cert = false;
+    int since_best = 0;
+    bool stalled = false;
+    while (it < cap) {
+        t0 = wall_clock64();
+        affine_phase<T, NT, T>(P, rp, wy, wx, s_z, s_red);
+        const unsigned long long t1 = wall_clock64();
+        t_aff += t1 - t0;
+        long long voff = 0;
+        for (int bk = 0; bk < P.nblk; ++bk) {
+            const int off = P.blk_off[bk];
+            const int N = P.blk_N[bk];
+            if (N <= rp.rows_nmax) {
+                // rows split over the wavefronts, G, V and partial sums in LDS
+                project_block_rows<T, NT>(v + off, u + off, N, rp.warm_eig ? vstore + voff : nullptr,
+                                          rp.warm_eig && warm, s_mat, Tm, sc, rp.max_sweeps);
+                voff += (long long)N * N;
+                continue;
+            }
+            const int ld = N;
+            T *vc = rp.warm_eig ? vstore + voff : nullptr;
+            const bool wm = rp.warm_eig && warm;
+            const int gs = lanes_per_pair(rp, N);
+            T *g1 = Tm + (long long)P.nmax * P.nmax, *g2 = g1 + (long long)P.nmax * P.nmax;
+            if (N <= rp.lds_nmax)        // G and V in LDS
+                project_block<T, NT>(v + off, u + off, N, vc, wm, s_mat, s_mat + (long long)N * N, ld, Tm, s_sig,
+                                     sc, rp.max_sweeps, gs);
+            else if (N <= rp.lds_nmax_g)  // G in LDS, V in global scratch
+                project_block<T, NT>(v + off, u + off, N, vc, wm, s_mat, g1, ld, Tm, s_sig, sc, rp.max_sweeps, gs);
+            else                          // both in global scratch
+                project_block<T, NT>(v + off, u + off, N, vc, wm, g1, g2, ld, Tm, s_sig, sc, rp.max_sweeps, gs);
+            voff += (long long)N * N;
+        }
+        warm = rp.warm_eig != 0;
+        ++it;
+        const unsigned long long t2 = wall_clock64();
+        t_eig += t2 - t1;
+        if (rp.mode == RUN_SOLVE && it >= rp.min_iters &&
+            (it % rp.check_every == 0 || it == cap || it == rp.min_iters)) {
+            double pm[2] = {INFINITY, INFINITY};
+            status = residual_phase<T, NT>(P, rp.tol, s_red, it_warm + it, pm);
+            t_res += wall_clock64() - t2;
+            if (status) break;
+            if (trying && (!(P.tk[0] > 0.0) || it >= rp.warm_budget)) {
+                // the warm start failed its trial: restart from the cold start u = v = (0, 0, 1)
+                // with the full budget (the cold method as the fallback)
+                __syncthreads();
+                const int nu = P.nx + P.m;
+                for (int e = threadIdx.x; e < nu; e += NT) {
+                    u[e] = (T)0;
+                    if (e < P.nx) v[e] = (T)0;
+                }
+                if (threadIdx.x == 0) {
+                    P.tk[0] = 1.0;
+                    P.tk[1] = 1.0;
+                    P.tk[2] = 0.0;
+                    P.tk[3] = 0.0;
+                }
+                __syncthreads();
+                trying = false;
+                warm = false;
+                it_warm += it;
+                it = 0;
+                cap = rp.iters;
+                best = INFINITY;
+                best_ce = INFINITY;
+                was_cert = false;
+                since_best = 0;
+                continue;
+            }
+            // a phase that stops improving hands over (the FP32 phase of the mixed form):
+            // stalled once stall_checks checks in a row (three times as many while
+            // tau = 0) missed 0.99 x the best value of the measure of the current
+            // regime: the largest residual while tau > 0, the certificate error while
+            // tau = 0 (each best kept per regime; a change of regime restarts the count)
+            if (rp.stall_checks > 0) {
+                const bool cert = !isfinite(pm[0]);
+                bool better;
+                if (!cert) {
+                    better = pm[0] < 0.99 * best;
+                    best = fmin(best, pm[0]);
+                } else {
+                    better = !isfinite(pm[1]) || pm[1] < 0.99 * best_ce;
+                    best_ce = fmin(best_ce, pm[1]);
+                }
+                if (cert != was_cert) better = true;
+                was_cert = cert;
+                // the certificate error decays like 1/k with bumps, and the FP32
+                // iterate carries it down to about 5 tol: a longer window there
+                if (better) {
+                    since_best = 0;
+                } else if (++since_best >= (cert ? 3 * rp.stall_checks : rp.stall_checks)) {
+                    stalled = true;
+                    break;
+                }
+            }
+        }
+    }
+    if (rp.mode == RUN_STEP || status == 0) {
+        status = residual_phase<T, NT>(P, rp.tol, s_red, it_warm + it);
+        if (rp.mode == RUN_SOLVE && status == 0 && !stalled && threadIdx.x == 0) P.out[SOS_OUT_STATUS] = 4;
+    }
+    if (threadIdx.x == 0) {
+        P.out[SOS_OUT_T_AFFINE] = (double)t_aff;
+        P.out[SOS_OUT_T_EIG] = (double)t_eig;
+        P.out[SOS_OUT_T_RES] = (double)t_res;
+        P.out[SOS_OUT_SWEEPS] = (it > 0 && P.nblk > 0) ? (double)(*sc.s_sweeps) / ((double)it * P.nblk) : 0.0;
+        P.out[SOS_OUT_TOTAL] = (rp.accumulate ? P.out[SOS_OUT_TOTAL] : 0.0) + it_warm + it;
+        if (!rp.accumulate) P.out[SOS_OUT_WARM] = it_warm;
+        if (it > 0) P.tk[2] = rp.warm_eig ? 1.0 : 0.0;
+        if (rp.mode == RUN_SOLVE) P.tk[3] = 0.0;   // judged (or never under judgement)
+    }
+    __syncthreads();
+    return status;
+}
+
 template <typename T, int NT>
 __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
     __shared__ int s_idx;
@@ -1130,14 +1281,6 @@ __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
     __shared__ int s_sweeps;
     __shared__ double s_red[4 * (NT / 64)];
     extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
-    // dynamic LDS: sigma (eig_ld values), then G and V of blocks with N <= rp.lds_nmax,
-    // or G alone for blocks with N <= rp.lds_nmax_g
-    typename Lds<T>::type *s_sig = as_lds<T>(dyn_lds);
-    typename Lds<T>::type *s_mat = as_lds<T>(dyn_lds + rp.lds_mat_off);
-    // the affine step's k-vector and the Schur solve's partial sums share the eigen
-    // region: the two phases are separated by barriers
-    double *s_z = reinterpret_cast<double *>(dyn_lds + rp.lds_mat_off);
-
     char *wbase = reinterpret_cast<char *>(rp.work) + (long long)blockIdx.x * rp.work_stride;
     char *ebase = reinterpret_cast<char *>(rp.eig) + (long long)blockIdx.x * rp.eig_stride;
     EigScratch sc;
@@ -1146,7 +1289,6 @@ __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
     sc.s_red = s_red;
     sc.jtol = rp.jacobi_tol;
     if (rp.ts && threadIdx.x == 0) atomicMin(&rp.ts[0], (unsigned long long)wall_clock64());
-
     for (;;) {
         if (threadIdx.x == 0) s_idx = atomicAdd(rp.counter, 1);
         __syncthreads();
@@ -1154,144 +1296,51 @@ __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
         __syncthreads();
         if (idx >= rp.count) break;
         const int pid = __builtin_amdgcn_readfirstlane(rp.order[idx]);
-        const ProbDesc &P = rp.probs[pid];
-        T *wy = reinterpret_cast<T *>(wbase);
-        T *wx = wy + ((P.m + 63) & ~63);
-        T *Tm = reinterpret_cast<T *>(ebase);
-        T *u = TS<T>::u(P);
-        T *v = TS<T>::v(P);
-        T *vstore = TS<T>::vstore(P);
-        bool warm = P.tk[2] != 0.0;
-        if (threadIdx.x == 0) s_sweeps = 0;
-
-        int it = 0;
-        int status = 0;
-        unsigned long long t_aff = 0, t_eig = 0, t_res = 0, t0 = 0;   // wall-clock ticks by phase
-        // iteration budget: in an accumulating (second) phase, what the first phase left over
-        int cap = rp.iters;
-        if (rp.accumulate) {
-            cap = rp.iters + (int)P.out[SOS_OUT_WARM] - (int)P.out[SOS_OUT_TOTAL];
-            if (cap < rp.min_iters) cap = rp.min_iters;
-        }
-        // a warm start under judgement (first launch of a solve only)
-        bool trying = rp.mode == RUN_SOLVE && !rp.accumulate && rp.warm_budget > 0 && P.tk[3] != 0.0;
-        int it_warm = 0;   // iterations of an abandoned warm attempt
-        double best = INFINITY, best_ce = INFINITY;
-        bool was_cert = false;
-        int since_best = 0;
-        bool stalled = false;
-        while (it < cap) {
-            t0 = wall_clock64();
-            affine_phase<T, NT, T>(P, rp, wy, wx, s_z, s_red);
-            const unsigned long long t1 = wall_clock64();
-            t_aff += t1 - t0;
-            long long voff = 0;
-            for (int bk = 0; bk < P.nblk; ++bk) {
-                const int off = P.blk_off[bk];
-                const int N = P.blk_N[bk];
-                if (N <= rp.rows_nmax) {
-                    // rows split over the wavefronts, G, V and partial sums in LDS
-                    project_block_rows<T, NT>(v + off, u + off, N, rp.warm_eig ? vstore + voff : nullptr,
-                                              rp.warm_eig && warm, s_mat, Tm, sc, rp.max_sweeps);
-                    voff += (long long)N * N;
-                    continue;
-                }
-                const int ld = N;
-                T *vc = rp.warm_eig ? vstore + voff : nullptr;
-                const bool wm = rp.warm_eig && warm;
-                const int gs = lanes_per_pair(rp, N);
-                T *g1 = Tm + (long long)P.nmax * P.nmax, *g2 = g1 + (long long)P.nmax * P.nmax;
-                if (N <= rp.lds_nmax)        // G and V in LDS
-                    project_block<T, NT>(v + off, u + off, N, vc, wm, s_mat, s_mat + (long long)N * N, ld, Tm, s_sig,
-                                         sc, rp.max_sweeps, gs);
-                else if (N <= rp.lds_nmax_g)  // G in LDS, V in global scratch
-                    project_block<T, NT>(v + off, u + off, N, vc, wm, s_mat, g1, ld, Tm, s_sig, sc, rp.max_sweeps, gs);
-                else                          // both in global scratch
-                    project_block<T, NT>(v + off, u + off, N, vc, wm, g1, g2, ld, Tm, s_sig, sc, rp.max_sweeps, gs);
-                voff += (long long)N * N;
-            }
-            warm = rp.warm_eig != 0;
-            ++it;
-            const unsigned long long t2 = wall_clock64();
-            t_eig += t2 - t1;
-            if (rp.mode == RUN_SOLVE && it >= rp.min_iters &&
-                (it % rp.check_every == 0 || it == cap || it == rp.min_iters)) {
-                double pm[2] = {INFINITY, INFINITY};
-                status = residual_phase<T, NT>(P, rp.tol, s_red, it_warm + it, pm);
-                t_res += wall_clock64() - t2;
-                if (status) break;
-                if (trying && (!(P.tk[0] > 0.0) || it >= rp.warm_budget)) {
-                    // the warm start failed its trial: restart from the cold start u = v = (0, 0, 1)
-                    // with the full budget (the cold method as the fallback)
-                    __syncthreads();
-                    const int nu = P.nx + P.m;
-                    for (int e = threadIdx.x; e < nu; e += NT) {
-                        u[e] = (T)0;
-                        if (e < P.nx) v[e] = (T)0;
-                    }
-                    if (threadIdx.x == 0) {
-                        P.tk[0] = 1.0;
-                        P.tk[1] = 1.0;
-                        P.tk[2] = 0.0;
-                        P.tk[3] = 0.0;
-                    }
-                    __syncthreads();
-                    trying = false;
-                    warm = false;
-                    it_warm += it;
-                    it = 0;
-                    cap = rp.iters;
-                    best = INFINITY;
-                    best_ce = INFINITY;
-                    was_cert = false;
-                    since_best = 0;
-                    continue;
-                }
-                // a phase that stops improving hands over (the FP32 phase of the mixed form):
-                // stalled once stall_checks checks in a row (three times as many while
-                // tau = 0) missed 0.99 x the best value of the measure of the current
-                // regime: the largest residual while tau > 0, the certificate error while
-                // tau = 0 (each best kept per regime; a change of regime restarts the count)
-                if (rp.stall_checks > 0) {
-                    const bool cert = !isfinite(pm[0]);
-                    bool better;
-                    if (!cert) {
-                        better = pm[0] < 0.99 * best;
-                        best = fmin(best, pm[0]);
-                    } else {
-                        better = !isfinite(pm[1]) || pm[1] < 0.99 * best_ce;
-                        best_ce = fmin(best_ce, pm[1]);
-                    }
-                    if (cert != was_cert) better = true;
-                    was_cert = cert;
-                    // the certificate error decays like 1/k with bumps, and the FP32
-                    // iterate carries it down to about 5 tol: a longer window there
-                    if (better) {
-                        since_best = 0;
-                    } else if (++since_best >= (cert ? 3 * rp.stall_checks : rp.stall_checks)) {
-                        stalled = true;
-                        break;
-                    }
-                }
-            }
-        }
-        if (rp.mode == RUN_STEP || status == 0) {
-            status = residual_phase<T, NT>(P, rp.tol, s_red, it_warm + it);
-            if (rp.mode == RUN_SOLVE && status == 0 && !stalled && threadIdx.x == 0) P.out[SOS_OUT_STATUS] = 4;
-        }
-        if (threadIdx.x == 0) {
-            P.out[SOS_OUT_T_AFFINE] = (double)t_aff;
-            P.out[SOS_OUT_T_EIG] = (double)t_eig;
-            P.out[SOS_OUT_T_RES] = (double)t_res;
-            P.out[SOS_OUT_SWEEPS] = (it > 0 && P.nblk > 0) ? (double)s_sweeps / ((double)it * P.nblk) : 0.0;
-            P.out[SOS_OUT_TOTAL] = (rp.accumulate ? P.out[SOS_OUT_TOTAL] : 0.0) + it_warm + it;
-            if (!rp.accumulate) P.out[SOS_OUT_WARM] = it_warm;
-            if (it > 0) P.tk[2] = rp.warm_eig ? 1.0 : 0.0;
-            if (rp.mode == RUN_SOLVE) P.tk[3] = 0.0;   // judged (or never under judgement)
-        }
-        __syncthreads();
+        run_phase<T, NT>(rp.probs[pid], rp, wbase, ebase, dyn_lds, sc);
     }
     if (rp.ts && threadIdx.x == 0) atomicMax(&rp.ts[1], (unsigned long long)wall_clock64());
+}
+
+// The mixed form in one launch: each problem runs its FP32 phase (rp32: to tol, a
+// certificate, a stall or the budget), its iterate is widened to FP64 in place, and the
+// same workgroup continues at once with the FP64 phase (rp64: the rest of the budget, at
+// least the polish iterations).  No problem waits for another's FP32 phase to end.
+template <int NT>
+__global__ __launch_bounds__(NT, 2) void admm_mixed(RunParams rp32, RunParams rp64) {
+    __shared__ int s_idx;
+    __shared__ int s_flag;
+    __shared__ int s_sweeps;
+    __shared__ double s_red[4 * (NT / 64)];
+    extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+    char *wbase = reinterpret_cast<char *>(rp32.work) + (long long)blockIdx.x * rp32.work_stride;
+    char *ebase = reinterpret_cast<char *>(rp32.eig) + (long long)blockIdx.x * rp32.eig_stride;
+    EigScratch sc;
+    sc.s_flag = as_lds<int>((void *)&s_flag);
+    sc.s_sweeps = as_lds<int>((void *)&s_sweeps);
+    sc.s_red = s_red;
+    if (rp32.ts && threadIdx.x == 0) atomicMin(&rp32.ts[0], (unsigned long long)wall_clock64());
+    for (;;) {
+        if (threadIdx.x == 0) s_idx = atomicAdd(rp32.counter, 1);
+        __syncthreads();
+        const int idx = __builtin_amdgcn_readfirstlane(s_idx);
+        __syncthreads();
+        if (idx >= rp32.count) break;
+        const int pid = __builtin_amdgcn_readfirstlane(rp32.order[idx]);
+        const ProbDesc &P = rp32.probs[pid];
+        sc.jtol = rp32.jacobi_tol;
+        run_phase<float, NT>(P, rp32, wbase, ebase, dyn_lds, sc);
+        // widen the iterate; the cached FP64 eigenvectors are stale
+        const int nu = P.nx + P.m;
+        for (int e = threadIdx.x; e < nu; e += NT) {
+            P.u64[e] = (double)P.u32[e];
+            if (e < P.nx) P.v64[e] = (double)P.v32[e];
+        }
+        if (threadIdx.x == 0) P.tk[2] = 0.0;
+        __syncthreads();
+        sc.jtol = rp64.jacobi_tol;
+        run_phase<double, NT>(P, rp64, wbase, ebase, dyn_lds, sc);
+    }
+    if (rp32.ts && threadIdx.x == 0) atomicMax(&rp32.ts[1], (unsigned long long)wall_clock64());
 }
 
 // Learned warm start: from a predicted (xi, y) (FP32 rows, internal layout), set
@@ -1480,7 +1529,34 @@ int launch_t(int grid, const RunParams &rp_in, hipStream_t st) {
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
+template <int NT>
+int launch_mixed(int grid, const RunParams &rp32_in, const RunParams &rp64_in, hipStream_t st) {
+    RunParams rp32 = rp32_in, rp64 = rp64_in;
+    size_t lds32 = 0, lds64 = 0;
+    lds_layout<float>(rp32.eig_ld, rp32.lds_budget, NT / 64, rp32.lds_mat_off, rp32.lds_nmax, rp32.lds_nmax_g, lds32,
+                      rp32.eig_wave, rp32.rows_nmax);
+    lds_layout<double>(rp64.eig_ld, rp64.lds_budget, NT / 64, rp64.lds_mat_off, rp64.lds_nmax, rp64.lds_nmax_g, lds64,
+                       rp64.eig_wave, rp64.rows_nmax);
+    const size_t lds = lds32 > lds64 ? lds32 : lds64;
+    if (lds > 64 * 1024) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&admm_mixed<NT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+    }
+    hipLaunchKernelGGL((admm_mixed<NT>), dim3(grid), dim3(NT), lds, st, rp32, rp64);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
 }   // namespace
+
+int sos_launch_admm_mixed(int threads, int grid, const RunParams &rp32, const RunParams &rp64, void *stream) {
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    switch (threads) {
+        case 256: return launch_mixed<256>(grid, rp32, rp64, st);
+        case 512: return launch_mixed<512>(grid, rp32, rp64, st);
+    }
+    return -1;   // other widths: the caller uses the two-launch form
+}
 
 int sos_launch_admm(int fp64, int threads, int grid, const RunParams &rp, void *stream) {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);

@@ -273,3 +273,22 @@ def test_autotuner_writes_a_schedule_the_batch_accepts(B):
     for a, b in zip(out[0][1], out[1][1]):
         if a is not None:
             assert abs(a - b) <= 5e-4 * max(1.0, abs(a))
+
+
+def test_mixed_one_launch_equals_two_launches(B):
+    # the mixed form in one launch (each problem widens to FP64 as soon as its own FP32
+    # phase ends) computes exactly what the two-launch form does
+    probs = [F.pop_unconstrained(n, sd) for n, sd in ((4, 0), (4, 1), (5, 4))] + [F.pop_ball(3, 5), F.lyapunov(3)]
+    s = B.sos_default_settings(tol=1e-4, max_iters=2000, precision=B.SOS_FP32_MIXED, polish_iters=1)
+    res = []
+    for one in (1, 0):
+        works = [B.setup_problem(p, s) for p in probs]
+        bt = B.sos_batch_setup(works, f'{{"one_launch": {one}}}')
+        infos = B.sos_batch_solve(bt)
+        res.append(([(i["status"], i["iters"], i["polish_iters"]) for i in infos], [B.sos_get_iterate(w) for w in works]))
+        print(f"[mixed] one_launch={one}: {res[-1][0]}; launch {B.sos_batch_phase_ms(bt, 0):.1f} + "
+              f"{B.sos_batch_phase_ms(bt, 1):.1f} ms", flush=True)
+        bt.free()
+    assert res[0][0] == res[1][0]
+    for (u1, v1), (u2, v2) in zip(res[0][1], res[1][1]):
+        assert np.array_equal(u1, u2) and np.array_equal(v1, v2)
