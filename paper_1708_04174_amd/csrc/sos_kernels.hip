@@ -185,7 +185,7 @@ __device__ __noinline__ void affine_phase(const ProbDesc &P, const RunParams &rp
     }
     __syncthreads();
 
-    // P2: q = A_f^T x, then the cached FP64 Cholesky solve
+    // P2: q = A_f^T x, then z = S^{-1} q in FP64
     if (k > 0) {
         const int *__restrict__ fptr = P.fptr;
         const int *__restrict__ frow = P.frow;
@@ -470,7 +470,7 @@ __device__ __forceinline__ bool os_rotate_pair(GP G, int ldg, VP V, int ldv, int
 // columns of G = W V mutually orthogonal by plane rotations applied to G and V alike;
 // then V holds eigenvectors of W and Sigma = diag(|g_j|) = |eigenvalues| (for a symmetric W
 // the right singular vectors are eigenvectors, and the formula holds within any group of
-// equal |lambda|).  Round-robin parallel ordering, one wavefront per column pair, one
+// equal |lambda|).  Round-robin parallel ordering, a group of lanes per column pair, one
 // barrier per round.  With a cached V from the previous ADMM iteration (warm) the sweeps
 // start from G = W V, which is nearly orthogonal once the iterates settle.
 // G, V: column-major N x N (column j at j*ld), in LDS or global scratch; Tm: N x N global.
@@ -661,7 +661,7 @@ template <typename T> __device__ __forceinline__ T hsum(typename V16<T>::v x);
 template <> __device__ __forceinline__ float hsum<float>(V16<float>::v x) { return (x.x + x.y) + (x.z + x.w); }
 template <> __device__ __forceinline__ double hsum<double>(V16<double>::v x) { return x.x + x.y; }
 
-// Between Jacobi rounds of one wavefront: a code-motion barrier only.  A wavefront's LDS
+// Between Jacobi rounds, within a wavefront: a code-motion barrier only.  A wavefront's LDS
 // operations are performed in issue order, so a read issued after a write (by any lane of
 // the same wavefront) returns the written value without waiting for the write to finish.
 __device__ __forceinline__ void wave_order() { __builtin_amdgcn_wave_barrier(); }
@@ -1483,8 +1483,10 @@ __global__ void reset_state(const ProbDesc *probs, int count) {
     }
 }
 
-// Dynamic LDS layout for element type T: sigma, then G and V (both N x N) for blocks up to
-// lds_nmax, or G alone for blocks up to lds_nmax_g; larger blocks work in global scratch.
+// Dynamic LDS layout for element type T: sigma, then the eigen region: the rows form's G, V,
+// partial records and sigma for blocks up to rows_nmax (eig_wave 2); for the lane-group form,
+// G and V (both N x N) up to lds_nmax, or G alone up to lds_nmax_g (larger blocks work in
+// global scratch).  The affine step's k-vector and partial sums alias the eigen region.
 template <typename T>
 void lds_layout(int eig_ld, int lds_budget, int nw, int &mat_off, int &lds_nmax, int &lds_nmax_g, size_t &bytes,
                 int eig_wave, int &rows_nmax) {
@@ -1499,7 +1501,6 @@ void lds_layout(int eig_ld, int lds_budget, int nw, int &mat_off, int &lds_nmax,
     const size_t need2 = lds_nmax ? off + sizeof(T) * 2 * (size_t)lds_nmax * lds_nmax : off;
     const size_t need1 = lds_nmax_g ? off + sizeof(T) * (size_t)lds_nmax_g * lds_nmax_g : off;
     bytes = need2 > need1 ? need2 : need1;
-    // one-wavefront form: G and V with the padded leading dimension
     // rows-per-wavefront form (eig_wave 2): G, V, partial records and sigma of one block
     rows_nmax = 0;
     size_t need3 = off;
