@@ -73,6 +73,22 @@ def cpu_baseline(probs, budget_s: float, tol: float):
                       f"{solved} counted in {el:.1f} s ({', '.join(names[:6])}{', ...' if len(names) > 6 else ''})"}
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter runs,
+    or None when none were taken for this kernel and workload or the kernel source changed
+    since they were."""
+    import hashlib
+    f = os.path.join(ROOT, "profiles", "admm_mixed_lyapunov_512_traffic.json")
+    if not os.path.exists(f):
+        return None
+    rec = json.load(open(f))
+    src = open(os.path.join(ROOT, "paper_1708_04174_amd", "csrc", "sos_kernels.hip"), "rb").read()
+    if rec.get("kernel") != kernel or rec.get("workload") != workload or \
+            rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return float(rec["hbm_bytes_per_launch"])
+
+
 def load_schedule(name: str, override):
     """The launch schedule as a JSON string: --schedule names a file or is inline JSON."""
     if override:
@@ -268,8 +284,11 @@ def main():
     flops = f32 + f64
     peak = flops / (f32 / PEAK_FP32_TFLOPS + f64 / PEAK_FP64_TFLOPS) if flops > 0 else PEAK_FP32_TFLOPS
     achieved = flops / (k_ms / 1e3) / 1e12 if k_ms > 0 else None
+    traffic = measured_traffic(kname, args.workload)
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": (achieved / peak) if achieved else None, "traffic": None,
+                "frac": (achieved / peak) if achieved else None, "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "traffic_GBps": (traffic / (k_ms / 1e3) / 1e9) if (traffic and k_ms > 0) else None,
                 "kernel": kname, "kernel_ms": k_ms, "launches_per_step": len(launches),
                 "launch_ms": [x[0] for x in launches], "algorithmic_flops_per_launch": flops,
                 "fp32_flops_per_launch": f32, "fp64_flops_per_launch": f64,
