@@ -93,6 +93,12 @@ typedef struct {
     int32_t polish_iters;    /* FP64 iterations after an FP32 solve (>= 1 for SOS_FP32_MIXED) */
     int32_t partition;       /* SOS_PART_PAPER | SOS_PART_COLUMNS */
     int32_t block_threads;   /* threads per workgroup: 0 = default (512), else 64..1024, multiple of 64 */
+    int32_t eig_form;        /* eigensolver of sos_step / sos_solve: 0 = library default (the
+                                lane-group form for N < 96, 8 lanes per column pair for N >= 64,
+                                the rows-over-wavefronts form from N = 96 for blocks that fit in
+                                LDS), 1 = rows form for every block that fits in LDS, 2 = lane-group
+                                form for every block.  Batches take theirs from the schedule.
+                                Out of 0..2: SOS_E_INVAL. */
     int32_t warm_budget;     /* 0: a warm-started solve keeps its start to the end.  > 0: a solve that
                                 starts from sos_warm_start / sos_batch_warm_start and has neither
                                 converged after warm_budget iterations nor kept tau > 0 at a residual
@@ -173,9 +179,12 @@ void sos_free(sos_work *w);
    {"block_threads": 512, "wg_per_cu": 1, "max_sweeps": 60, "use_graph": 1, "eig_wave": 2}.
    Keys: block_threads, wg_per_cu, max_sweeps, warm_eig (Jacobi warm start from the last
    eigenvectors), use_graph (capture the launches in a hipGraph), eig_wave (2: rows form
-   for blocks that fit in LDS, 0: lane-group form for all), lds_kb, gs_n32 .. gs_big (lanes
-   per column pair of the lane-group form by block size), one_launch (mixed form: 1 runs
-   both phases in one launch, 0 in two).  The handles must outlive the batch. */
+   for blocks that fit in LDS, 0: lane-group form for all), rows_nmin (eig_wave 2: blocks
+   with N below it still take the lane-group form), lds_kb, gs_n32 .. gs_big (lanes per
+   column pair of the lane-group form by block size), one_launch (mixed form: 1 runs both
+   phases in one launch, 0 in two).  Keys left out take the choice sos_solve makes with
+   eig_form 0, so a batch without a schedule retraces single solves bitwise.  The handles
+   must outlive the batch. */
 int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_json,
                     sos_batch **out);
 

@@ -65,7 +65,8 @@ def tune(probs, precision: int = 0, iters: int = 40, sample: int = 64, log=print
     # fixed-length runs: an unreachable tolerance makes every problem run `iters` iterations
     # lanes per pair are tuned with the lane-group form on every block (eig_wave 0), so that
     # each bucket's choice is timed where it applies
-    base = {"block_threads": 512, "wg_per_cu": 1, "max_sweeps": 60, "warm_eig": 1, "use_graph": 0, "eig_wave": 0}
+    base = {"block_threads": 512, "wg_per_cu": 1, "max_sweeps": 60, "warm_eig": 1, "use_graph": 0, "eig_wave": 0,
+            "rows_nmin": 0}
     byb = defaultdict(list)
     for i, p in enumerate(probs):
         for b in sorted({bucket_of(N) for N in p.psd_dims if N > 1}):
@@ -90,15 +91,19 @@ def tune(probs, precision: int = 0, iters: int = 40, sample: int = 64, log=print
     pick = rng.choice(len(probs), size=min(len(probs), 4 * sample), replace=False)
     works = _fixed_length_works([probs[i] for i in pick], iters)
     res = {}
-    for ew in (2, 0):
+    # eigensolver forms: (eig_wave, rows_nmin) = rows form for every block that fits in LDS,
+    # rows form from N = 96 on (lane groups below), lane groups for every block
+    for ew, rmin in ((2, 0), (2, 96), (0, 0)):
         for thr in (256, 512):
             for wpc in (1, 2):
                 s = dict(sched)
-                s["eig_wave"], s["block_threads"], s["wg_per_cu"] = ew, thr, wpc
-                res[(ew, thr, wpc)] = time_schedule(works, s)
-                log(f"[tune] eigensolver form {ew} threads {thr} wg/CU {wpc}: {res[(ew, thr, wpc)]:.2f} ms")
-    ew, thr, wpc = min(res, key=res.get)
-    sched["eig_wave"], sched["block_threads"], sched["wg_per_cu"] = ew, thr, wpc
+                s["eig_wave"], s["rows_nmin"], s["block_threads"], s["wg_per_cu"] = ew, rmin, thr, wpc
+                key = (ew, rmin, thr, wpc)
+                res[key] = time_schedule(works, s)
+                log(f"[tune] eigensolver form {ew} rows from N={rmin} threads {thr} wg/CU {wpc}: "
+                    f"{res[key]:.2f} ms")
+    ew, rmin, thr, wpc = min(res, key=res.get)
+    sched["eig_wave"], sched["rows_nmin"], sched["block_threads"], sched["wg_per_cu"] = ew, rmin, thr, wpc
     sched["use_graph"] = 1
     for ws in works:
         for w in ws:

@@ -22,6 +22,12 @@ thread_local std::string g_setup_error;
 
 // dynamic LDS a solver launch may take (gfx950: 160 KiB per workgroup, minus the static part)
 const int kLdsBudget = 159 * 1024;   // of the 160 KiB per workgroup, the rest for static LDS
+// Default eigensolver choice (single solves and schedules without these keys): the lane-group
+// form below N = 96, where it measured faster in both precisions, and the rows-over-wavefronts
+// form from 96 on for blocks that fit in LDS; lanes per column pair by block-size bucket
+// (N < 32, 64, 96, 128, 192, 256, larger): 8 for 64 <= N < 128, as the autotuner picks there.
+constexpr int kRowsNmin = 96;
+constexpr int kLanesPerPair[7] = {16, 16, 8, 8, 16, 16, 16};
 // mixed form: the FP32 phase hands over after this many residual checks without a 10 % gain.
 // An FP32-stored iterate has a residual floor of about eps_32 |A| |y| / tau (above 1e-4 on the
 // Lyapunov family), so the hand-over should come soon after the floor is reached.
@@ -119,7 +125,7 @@ struct sos_batch {
     unsigned long long *d_ts = nullptr;   // wall-clock stamps of the solve and polish kernels
     double last_ms = 0.0, phase_ms[2] = {0.0, 0.0};
     bool use_graph = true;
-    int warm_eig = 1, lds_budget = 0, eig_wave = 2;
+    int warm_eig = 1, lds_budget = 0, eig_wave = 2, rows_nmin = 0;
     int one_launch = 1;   // mixed form: both phases in one launch (threads 256 or 512)
     bool used_one_launch = false;
     int gs_bucket[7] = {16, 16, 16, 16, 16, 16, 16};
@@ -137,6 +143,7 @@ void default_settings(sos_settings *s) {
     s->polish_iters = 1;
     s->partition = SOS_PART_PAPER;
     s->block_threads = 0;
+    s->eig_form = 0;
     s->warm_budget = 0;
 }
 
@@ -149,6 +156,7 @@ void check_settings(const sos_settings &s) {
         throw Status(SOS_E_INVAL, "block_threads must be 0 or a power of two in 64..1024");
     if (s.precision == SOS_FP32_MIXED && s.polish_iters < 1) throw Status(SOS_E_INVAL, "polish_iters >= 1 required");
     if (s.warm_budget < 0) throw Status(SOS_E_INVAL, "warm_budget must be >= 0");
+    if (s.eig_form < 0 || s.eig_form > 2) throw Status(SOS_E_INVAL, "eig_form must be 0, 1 or 2");
 }
 
 // Dense Cholesky of the k x k SPD matrix S (row-major), lower factor in place.
@@ -515,9 +523,10 @@ RunParams single_params(sos_work *w, int mode, int iters, int min_iters, double 
     rp.eig_ld = w->eig_ld;
     rp.max_sweeps = 60;
     rp.warm_eig = 1;
-    rp.eig_wave = 2;
     rp.lds_budget = kLdsBudget;
-    for (int i = 0; i < 7; ++i) rp.gs_bucket[i] = 16;
+    for (int i = 0; i < 7; ++i) rp.gs_bucket[i] = kLanesPerPair[i];
+    rp.eig_wave = w->st.eig_form == 2 ? 0 : 2;
+    rp.rows_nmin = w->st.eig_form == 0 ? kRowsNmin : 0;
     return rp;
 }
 
@@ -861,6 +870,8 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         B->warm_eig = (int)json_num(schedule_json, "warm_eig", 1);
         B->eig_wave = (int)json_num(schedule_json, "eig_wave", 2);
         B->one_launch = (int)json_num(schedule_json, "one_launch", 1);
+        B->rows_nmin = (int)json_num(schedule_json, "rows_nmin", kRowsNmin);
+        if (B->rows_nmin < 0) throw Status(SOS_E_INVAL, "schedule rows_nmin must be >= 0");
         if (B->eig_wave != 0 && B->eig_wave != 2)
             throw Status(SOS_E_INVAL, "schedule eig_wave must be 0 (lane groups) or 2 (rows over wavefronts)");
         // LDS per workgroup: what wg_per_cu resident workgroups can share (160 KiB per CU, less
@@ -870,7 +881,7 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         if (B->lds_budget < 0 || B->lds_budget > kLdsBudget) throw Status(SOS_E_INVAL, "schedule lds_kb out of range");
         static const char *gs_keys[7] = {"gs_n32", "gs_n64", "gs_n96", "gs_n128", "gs_n192", "gs_n256", "gs_big"};
         for (int i = 0; i < 7; ++i) {
-            B->gs_bucket[i] = (int)json_num(schedule_json, gs_keys[i], 16);
+            B->gs_bucket[i] = (int)json_num(schedule_json, gs_keys[i], kLanesPerPair[i]);
             if (B->gs_bucket[i] != 8 && B->gs_bucket[i] != 16 && B->gs_bucket[i] != 32)
                 throw Status(SOS_E_INVAL, "schedule lanes per pair must be 8, 16 or 32");
         }
@@ -946,6 +957,7 @@ static RunParams batch_params(sos_batch *B, int mode, int iters, int min_iters, 
     rp.max_sweeps = B->max_sweeps;
     rp.warm_eig = B->warm_eig;
     rp.eig_wave = B->eig_wave;
+    rp.rows_nmin = B->rows_nmin;
     rp.lds_budget = B->lds_budget;
     for (int i = 0; i < 7; ++i) rp.gs_bucket[i] = B->gs_bucket[i];
     return rp;

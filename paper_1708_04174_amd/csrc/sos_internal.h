@@ -86,6 +86,7 @@ struct RunParams {
     int eig_wave;           // 2: blocks that fit in LDS use the rows-over-wavefronts eigensolver;
                             // 0: every block uses the lane-group form
     int lds_mat_off, lds_nmax, lds_nmax_g, rows_nmax;   // filled in by the launcher
+    int rows_nmin;          // eig_wave 2: blocks with N below this still take the lane-group form
     int accumulate;         // 0: out[TOTAL] = iterations of this launch; 1: out[TOTAL] += them, and the
                             //    iteration budget is iters + out[WARM] - out[TOTAL] (at least min_iters)
     int warm_budget;        // > 0 (first launch of a solve): restart a warm start (tk[3] = 1) from the cold

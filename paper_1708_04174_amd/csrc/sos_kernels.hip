@@ -399,9 +399,10 @@ __device__ __forceinline__ bool jacobi_rot<double>(double al, double be, double 
 }
 
 // One-sided Jacobi rotation of the column pair (p, q) of G (and of V) by a group of GS
-// lanes; makes g_p and g_q orthogonal.  Returns true if a rotation was applied.
+// lanes; makes g_p and g_q orthogonal.  Returns 0 if no rotation was applied, 1 for a
+// rotation of relative coupling at most sqrt(tol), 2 for a larger one.
 template <typename T, int GS, typename GP, typename VP>
-__device__ __forceinline__ bool os_rotate_pair(GP G, int ldg, VP V, int ldv, int N, int p, int q, T tol, T atol) {
+__device__ __forceinline__ int os_rotate_pair(GP G, int ldg, VP V, int ldv, int N, int p, int q, T tol, T atol) {
     constexpr int RPL = 8;          // rows per lane held in registers (N <= 8 GS); larger N: streamed
     const int gl = threadIdx.x & (GS - 1);
     GP gp = G + (long long)p * ldg, gq = G + (long long)q * ldg;
@@ -429,7 +430,7 @@ __device__ __forceinline__ bool os_rotate_pair(GP G, int ldg, VP V, int ldv, int
         be = group_allsum<GS>(be);
         ga = group_allsum<GS>(ga);
         T cc, ss;
-        if (!jacobi_rot<T>(al, be, ga, tol * tol, atol * atol, cc, ss)) return false;
+        if (!jacobi_rot<T>(al, be, ga, tol * tol, atol * atol, cc, ss)) return 0;
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
             const int i = gl + GS * t;
@@ -440,7 +441,7 @@ __device__ __forceinline__ bool os_rotate_pair(GP G, int ldg, VP V, int ldv, int
                 vq[i] = ss * yp[t] + cc * yq[t];
             }
         }
-        return true;
+        return ga * ga > tol * (al * be) ? 2 : 1;
     }
     for (int i = gl; i < N; i += GS) {
         const T a = gp[i], b = gq[i];
@@ -452,7 +453,7 @@ __device__ __forceinline__ bool os_rotate_pair(GP G, int ldg, VP V, int ldv, int
     be = group_allsum<GS>(be);
     ga = group_allsum<GS>(ga);
     T cc, ss;
-    if (!jacobi_rot<T>(al, be, ga, tol * tol, atol * atol, cc, ss)) return false;
+    if (!jacobi_rot<T>(al, be, ga, tol * tol, atol * atol, cc, ss)) return 0;
     for (int i = gl; i < N; i += GS) {
         const T a = gp[i], b = gq[i];
         gp[i] = cc * a - ss * b;
@@ -461,7 +462,7 @@ __device__ __forceinline__ bool os_rotate_pair(GP G, int ldg, VP V, int ldv, int
         vp[i] = cc * c - ss * d;
         vq[i] = ss * c + cc * d;
     }
-    return true;
+    return ga * ga > tol * (al * be) ? 2 : 1;
 }
 
 // Projects one block: the lower triangle of W is read from vs, the lower triangle of
@@ -549,7 +550,10 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         if (tid == 0) *sc.s_flag = 0;
         __syncthreads();
-        int rotated = 0;
+        // big: some rotation of the sweep had relative coupling above sqrt(tol).  Without one
+        // the sweep is the last: cyclic Jacobi converges quadratically, so what such a sweep
+        // leaves is coupling of order tol, which the next sweep would not rotate
+        int big = 0;
         // lanes per column pair: a tile choice per block-size bucket (autotuned)
         if (gs == 8) {
             const int grp = tid / 8;
@@ -557,7 +561,7 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
                 for (int kk = grp; kk < H; kk += NT / 8) {
                     int p, q;
                     rr_pair(r, kk, M, p, q);
-                    if (q < N && os_rotate_pair<T, 8, GP, VP>(G, ld, V, ld, N, p, q, tol, atol)) rotated = 1;
+                    if (q < N && os_rotate_pair<T, 8, GP, VP>(G, ld, V, ld, N, p, q, tol, atol) == 2) big = 1;
                 }
                 __syncthreads();
             }
@@ -567,7 +571,7 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
                 for (int kk = grp; kk < H; kk += NT / 32) {
                     int p, q;
                     rr_pair(r, kk, M, p, q);
-                    if (q < N && os_rotate_pair<T, 32, GP, VP>(G, ld, V, ld, N, p, q, tol, atol)) rotated = 1;
+                    if (q < N && os_rotate_pair<T, 32, GP, VP>(G, ld, V, ld, N, p, q, tol, atol) == 2) big = 1;
                 }
                 __syncthreads();
             }
@@ -577,12 +581,12 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
                 for (int kk = grp; kk < H; kk += NT / 16) {
                     int p, q;
                     rr_pair(r, kk, M, p, q);
-                    if (q < N && os_rotate_pair<T, 16, GP, VP>(G, ld, V, ld, N, p, q, tol, atol)) rotated = 1;
+                    if (q < N && os_rotate_pair<T, 16, GP, VP>(G, ld, V, ld, N, p, q, tol, atol) == 2) big = 1;
                 }
                 __syncthreads();
             }
         }
-        if (rotated) *sc.s_flag = 1;
+        if (big) *sc.s_flag = 1;
         __syncthreads();
         const int any = *sc.s_flag;
         __syncthreads();
@@ -1170,7 +1174,7 @@ __device__ __noinline__ int run_phase(const ProbDesc &P, const RunParams &rp, ch
         for (int bk = 0; bk < P.nblk; ++bk) {
             const int off = P.blk_off[bk];
             const int N = P.blk_N[bk];
-            if (N <= rp.rows_nmax) {
+            if (N <= rp.rows_nmax && N >= rp.rows_nmin) {
                 // rows split over the wavefronts, G, V and partial sums in LDS
                 project_block_rows<T, NT>(v + off, u + off, N, rp.warm_eig ? vstore + voff : nullptr,
                                           rp.warm_eig && warm, s_mat, Tm, sc, rp.max_sweeps);
@@ -1393,7 +1397,7 @@ __global__ __launch_bounds__(NT) void warm_start_kernel(RunParams rp, const floa
         T *g1 = Tm + (long long)P.nmax * P.nmax, *g2 = g1 + (long long)P.nmax * P.nmax;
         for (int pass = 0; pass < 2; ++pass) {
             T *blk = (pass == 0 ? u : v) + off;   // projected in place via the scratch wx
-            if (N <= rp.rows_nmax) {
+            if (N <= rp.rows_nmax && N >= rp.rows_nmin) {
                 project_block_rows<T, NT>(blk, wx, N, nullptr, false, s_mat, Tm, sc, rp.max_sweeps);
             } else if (N <= rp.lds_nmax) {
                 project_block<T, NT>(blk, wx, N, nullptr, false, s_mat, s_mat + (long long)N * N, N, Tm, s_sig, sc,

@@ -71,6 +71,16 @@ def test_step_parity_launch_shapes(B, threads):
     _step_parity(B, F.pop_ball(3, 4), [3, 12], settings=s, tag=f"ball3_t{threads}")
 
 
+@pytest.mark.parametrize("form", [0, 1, 2])
+@pytest.mark.parametrize("case", ["c5", "pop_n14"])
+def test_step_parity_eigensolver_forms(B, form, case):
+    # single solves: default split at N = 96, rows form for every block, lane groups for every
+    # block; blocks of 28, 84 (Lyapunov) and 120 (quartic POP, n = 14)
+    prob = F.FAMILIES["c5"](1) if case == "c5" else F.pop_unconstrained(14, 0)
+    s = B.sos_default_settings(eig_form=form)
+    _step_parity(B, prob, [1, 4, 12], settings=s, tag=f"{case}_form{form}")
+
+
 def test_step_parity_c3_full_size(B):
     # constrained quartic POP on the unit ball, n = 16: Gram blocks 153 and 17, m = 4845, k = 154
     _step_parity(B, F.FAMILIES["c3"](0), [1, 3], tag="c3_full")
@@ -228,9 +238,10 @@ def test_single_mixed_precision_solve(B):
     assert abs(x[0] - r.x[0]) <= 5e-4 * max(1.0, abs(r.x[0]))
 
 
-@pytest.mark.parametrize("sched", ['{"eig_wave": 2}', '{"eig_wave": 0, "gs_n32": 8, "gs_n64": 32}',
+@pytest.mark.parametrize("sched", ['{}', '{"eig_wave": 2, "rows_nmin": 0}',
+                                   '{"eig_wave": 0, "gs_n32": 8, "gs_n64": 32}',
                                    '{"eig_wave": 0, "gs_n32": 16, "gs_n64": 8}',
-                                   '{"eig_wave": 2, "block_threads": 256, "wg_per_cu": 2}'])
+                                   '{"eig_wave": 2, "rows_nmin": 0, "block_threads": 256, "wg_per_cu": 2}'])
 def test_batch_eigensolver_forms_match_the_oracle(B, sched):
     # every eigensolver form a schedule can pick (rows over the wavefronts, lane groups
     # of 8, 16 or 32 per column pair) gives the oracle's gamma and status (FP64)
@@ -255,7 +266,7 @@ def test_autotuner_writes_a_schedule_the_batch_accepts(B):
     from paper_1708_04174_amd import autotune
     probs = [F.pop_unconstrained(n, sd) for n, sd in ((4, 0), (5, 1), (6, 2), (7, 3))]
     sched = autotune.tune(probs, B.SOS_FP32_MIXED, iters=10, sample=4, log=lambda m: print(m, flush=True))
-    for k in ("block_threads", "wg_per_cu", "eig_wave", "gs_n32", "use_graph"):
+    for k in ("block_threads", "wg_per_cu", "eig_wave", "rows_nmin", "gs_n32", "use_graph"):
         assert k in sched
     # the tuned schedule changes speed, not answers: statuses as with the default schedule,
     # gamma within the mixed-precision bound
