@@ -73,18 +73,31 @@ def cpu_baseline(probs, budget_s: float, tol: float):
                       f"{solved} counted in {el:.1f} s ({', '.join(names[:6])}{', ...' if len(names) > 6 else ''})"}
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter runs,
-    or None when none were taken for this kernel and workload or the kernel source changed
-    since they were."""
+COPY_PROBE_BYTES = 256 * 1024 * 1024
+
+
+def _sha256(path: str) -> str:
     import hashlib
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def _sha256_text(text: str) -> str:
+    import hashlib
+    return hashlib.sha256(text.encode()).hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str, sched):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter runs,
+    or None when none were taken for this kernel and workload, or the kernel source or the
+    schedule changed since they were."""
     f = os.path.join(ROOT, "profiles", "admm_mixed_lyapunov_512_traffic.json")
     if not os.path.exists(f):
         return None
     rec = json.load(open(f))
-    src = open(os.path.join(ROOT, "paper_1708_04174_amd", "csrc", "sos_kernels.hip"), "rb").read()
+    src = _sha256(os.path.join(ROOT, "paper_1708_04174_amd", "csrc", "sos_kernels.hip"))
+    sched_sha = _sha256_text(sched) if sched else None
     if rec.get("kernel") != kernel or rec.get("workload") != workload or \
-            rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+            rec.get("kernel_source_sha256") != src or rec.get("schedule_sha256") != sched_sha:
         return None
     return float(rec["hbm_bytes_per_launch"])
 
@@ -119,6 +132,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy a 256 MiB device buffer three times (the known-size kernel that "
+                         "calibrates the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -129,6 +145,14 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        a = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": COPY_PROBE_BYTES, "copies": 3}), flush=True)
+        return
     from paper_1708_04174_amd import binding as B
     from paper_1708_04174_amd import warmstart as W
     from paper_1708_04174_amd import workloads as WL
@@ -284,7 +308,7 @@ def main():
     flops = f32 + f64
     peak = flops / (f32 / PEAK_FP32_TFLOPS + f64 / PEAK_FP64_TFLOPS) if flops > 0 else PEAK_FP32_TFLOPS
     achieved = flops / (k_ms / 1e3) / 1e12 if k_ms > 0 else None
-    traffic = measured_traffic(kname, args.workload)
+    traffic = measured_traffic(kname, args.workload, sched)
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": (achieved / peak) if achieved else None, "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
