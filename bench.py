@@ -132,6 +132,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--dump-infos", default=None,
+                    help="write the per-problem records of the last timed step (status, iterations, "
+                         "queue start / finish in ms) to this JSON file")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 256 MiB device buffer three times (the known-size kernel that "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -256,6 +259,10 @@ def main():
         fbs.append(nfb)
         log(f"[bench] step {i}: {ms:.1f} ms, {ok}/{len(infos)} counted, fallbacks {nfb}, "
             f"solve kernel {kms[-1]:.1f} ms, separate FP64 kernel {pms[-1]:.1f} ms")
+    if args.dump_infos:
+        with open(args.dump_infos, "w") as f:
+            json.dump([dict(seed=int(sd), **{k: v for k, v in inf.items() if isinstance(v, (int, float, str))})
+                       for sd, inf in zip(test_seeds if lyap else range(len(infos)), infos)], f)
     total_ms = float(np.sum(step_ms))
     value = float(np.sum(counted)) / (total_ms / 1e3)
     statuses = {}

@@ -121,6 +121,9 @@ typedef struct {
     double  affine_ms, eig_ms, resid_ms;   /* device time of the last launch by phase (one workgroup's clock) */
     int32_t warm_iters;      /* iterations of a warm-started attempt abandoned for the cold restart
                                 (0: no restart; then iters counts the warm-started run itself) */
+    double  start_ms, end_ms;   /* sos_batch_solve: when a workgroup took the problem from the queue
+                                   and when it finished it, ms after the solve launch began (device
+                                   wall clock); 0 for single solves */
 } sos_info;
 
 /* Fills *s with tol 1e-4, max_iters 2000, check_every 10, alpha 1, SOS_FP64,

@@ -59,7 +59,8 @@ class sos_info(C.Structure):
                 ("res_pri", C.c_double), ("res_dual", C.c_double), ("gap", C.c_double),
                 ("tau", C.c_double), ("kappa", C.c_double), ("setup_ms", C.c_double),
                 ("solve_ms", C.c_double), ("eig_sweeps", C.c_double), ("affine_ms", C.c_double),
-                ("eig_ms", C.c_double), ("resid_ms", C.c_double), ("warm_iters", C.c_int32)]
+                ("eig_ms", C.c_double), ("resid_ms", C.c_double), ("warm_iters", C.c_int32),
+                ("start_ms", C.c_double), ("end_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}

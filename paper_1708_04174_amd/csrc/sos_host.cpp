@@ -563,6 +563,7 @@ void read_info(sos_work *w, const double *o, sos_info *info, int iters, int poli
     info->eig_ms = o[SOS_OUT_T_EIG] / khz;
     info->resid_ms = o[SOS_OUT_T_RES] / khz;
     info->warm_iters = (int)o[SOS_OUT_WARM];
+    info->start_ms = info->end_ms = 0.0;
 }
 
 template <typename F>
@@ -1042,6 +1043,10 @@ int sos_batch_solve(sos_batch *B, sos_info *infos) {
             w->last_ms = ms;
             const double *oi = o.data() + (size_t)i * SOS_OUT_N;
             read_info(w, oi, &infos[i], (int)oi[SOS_OUT_TOTAL], B->fp64 ? 0 : (int)oi[SOS_OUT_ITERS]);
+            if (ts[1] > ts[0]) {
+                infos[i].start_ms = (oi[SOS_OUT_T_START] - (double)ts[0]) / khz;
+                infos[i].end_ms = (oi[SOS_OUT_T_END] - (double)ts[0]) / khz;
+            }
         }
     });
     return rc;

@@ -60,7 +60,9 @@ struct ProbDesc {
 
 enum {
     SOS_OUT_STATUS = 0, SOS_OUT_ITERS, SOS_OUT_POBJ, SOS_OUT_DOBJ, SOS_OUT_RP, SOS_OUT_RD, SOS_OUT_GAP,
-    SOS_OUT_TAU, SOS_OUT_KAPPA, SOS_OUT_CX, SOS_OUT_BY, SOS_OUT_TOTAL, SOS_OUT_SWEEPS, SOS_OUT_T_AFFINE, SOS_OUT_T_EIG, SOS_OUT_T_RES, SOS_OUT_WARM, SOS_OUT_N
+    SOS_OUT_TAU, SOS_OUT_KAPPA, SOS_OUT_CX, SOS_OUT_BY, SOS_OUT_TOTAL, SOS_OUT_SWEEPS, SOS_OUT_T_AFFINE, SOS_OUT_T_EIG, SOS_OUT_T_RES, SOS_OUT_WARM,
+    SOS_OUT_T_START, SOS_OUT_T_END,   // device wall clock when a batch workgroup took the problem and finished it
+    SOS_OUT_N
 };
 
 enum { RUN_STEP = 0, RUN_SOLVE = 1 };

@@ -547,6 +547,7 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
     const T atol = (T)(jacobi_atol_factor(N) * TS<T>::eps * sqrt(fro2));
     const int M = N + (N & 1);
     const int H = M / 2;
+    int nsw = 0;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         if (tid == 0) *sc.s_flag = 0;
         __syncthreads();
@@ -590,9 +591,11 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
         __syncthreads();
         const int any = *sc.s_flag;
         __syncthreads();
-        if (tid == 0) *sc.s_sweeps += 1;
+        ++nsw;
         if (!any) break;
     }
+    // counted after the loop: no thread-0 block ends the body next to the one that begins it
+    if (tid == 0) *sc.s_sweeps += nsw;
     // sigma_j = |g_j|
     for (int j = wid; j < N; j += NW) {
         T s = 0;
@@ -1293,14 +1296,24 @@ __global__ __launch_bounds__(NT, 2) void admm_persistent(RunParams rp) {
     sc.s_red = s_red;
     sc.jtol = rp.jacobi_tol;
     if (rp.ts && threadIdx.x == 0) atomicMin(&rp.ts[0], (unsigned long long)wall_clock64());
+    int prev = -1;
     for (;;) {
-        if (threadIdx.x == 0) s_idx = atomicAdd(rp.counter, 1);
+        // one thread-0 block per pass: it stamps the end of the previous problem and takes the
+        // next one.  (A second thread-0 block at the end of the body, with only the back edge
+        // between it and this one, lets the compiler merge the two into a path that reaches
+        // the barrier below with part of wavefront 0 still outside it.)
+        if (threadIdx.x == 0) {
+            if (prev >= 0) rp.probs[prev].out[SOS_OUT_T_END] = (double)wall_clock64();
+            s_idx = atomicAdd(rp.counter, 1);
+        }
         __syncthreads();
         const int idx = __builtin_amdgcn_readfirstlane(s_idx);
         __syncthreads();
         if (idx >= rp.count) break;
         const int pid = __builtin_amdgcn_readfirstlane(rp.order[idx]);
+        if (threadIdx.x == 0 && !rp.accumulate) rp.probs[pid].out[SOS_OUT_T_START] = (double)wall_clock64();
         run_phase<T, NT>(rp.probs[pid], rp, wbase, ebase, dyn_lds, sc);
+        prev = pid;
     }
     if (rp.ts && threadIdx.x == 0) atomicMax(&rp.ts[1], (unsigned long long)wall_clock64());
 }
@@ -1323,8 +1336,13 @@ __global__ __launch_bounds__(NT, 2) void admm_mixed(RunParams rp32, RunParams rp
     sc.s_sweeps = as_lds<int>((void *)&s_sweeps);
     sc.s_red = s_red;
     if (rp32.ts && threadIdx.x == 0) atomicMin(&rp32.ts[0], (unsigned long long)wall_clock64());
+    int prev = -1;
     for (;;) {
-        if (threadIdx.x == 0) s_idx = atomicAdd(rp32.counter, 1);
+        // one thread-0 block per pass (see admm_persistent)
+        if (threadIdx.x == 0) {
+            if (prev >= 0) rp32.probs[prev].out[SOS_OUT_T_END] = (double)wall_clock64();
+            s_idx = atomicAdd(rp32.counter, 1);
+        }
         __syncthreads();
         const int idx = __builtin_amdgcn_readfirstlane(s_idx);
         __syncthreads();
@@ -1332,6 +1350,7 @@ __global__ __launch_bounds__(NT, 2) void admm_mixed(RunParams rp32, RunParams rp
         const int pid = __builtin_amdgcn_readfirstlane(rp32.order[idx]);
         const ProbDesc &P = rp32.probs[pid];
         sc.jtol = rp32.jacobi_tol;
+        if (threadIdx.x == 0) P.out[SOS_OUT_T_START] = (double)wall_clock64();
         run_phase<float, NT>(P, rp32, wbase, ebase, dyn_lds, sc);
         // widen the iterate; the cached FP64 eigenvectors are stale
         const int nu = P.nx + P.m;
@@ -1343,6 +1362,7 @@ __global__ __launch_bounds__(NT, 2) void admm_mixed(RunParams rp32, RunParams rp
         __syncthreads();
         sc.jtol = rp64.jacobi_tol;
         run_phase<double, NT>(P, rp64, wbase, ebase, dyn_lds, sc);
+        prev = pid;
     }
     if (rp32.ts && threadIdx.x == 0) atomicMax(&rp32.ts[1], (unsigned long long)wall_clock64());
 }
