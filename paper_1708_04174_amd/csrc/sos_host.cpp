@@ -27,6 +27,11 @@ const int kLdsBudget = 159 * 1024;   // of the 160 KiB per workgroup, the rest f
 // form from 96 on for blocks that fit in LDS; lanes per column pair by block-size bucket
 // (N < 32, 64, 96, 128, 192, 256, larger): 8 for 64 <= N < 128, as the autotuner picks there.
 constexpr int kRowsNmin = 96;
+// Jacobi coupling tolerance of the mixed form's FP64 phase (0: 16 eps of FP64).  That phase
+// only has to carry the iterate below the FP32 rounding floor (about 1e-7 relative), so
+// eigenvectors orthogonal to 1e-12 are ample; the sweeps stop once every coupling of a sweep
+// is under 1e-6 instead of under 6e-8.
+constexpr double kMixedJacobiTol64 = 1e-12;
 constexpr int kLanesPerPair[7] = {16, 16, 8, 8, 16, 16, 16};
 // mixed form: the FP32 phase hands over after this many residual checks without a 10 % gain.
 // An FP32-stored iterate has a residual floor of about eps_32 |A| |y| / tau (above 1e-4 on the
@@ -126,6 +131,7 @@ struct sos_batch {
     double last_ms = 0.0, phase_ms[2] = {0.0, 0.0};
     bool use_graph = true;
     int warm_eig = 1, lds_budget = 0, eig_wave = 2, rows_nmin = 0;
+    double jacobi_tol64 = 0.0;   // Jacobi tolerance of the mixed form's FP64 phase
     int one_launch = 1;   // mixed form: both phases in one launch (threads 256 or 512)
     bool used_one_launch = false;
     int gs_bucket[7] = {16, 16, 16, 16, 16, 16, 16};
@@ -742,6 +748,7 @@ int sos_solve(sos_work *w, sos_info *info) {
             set_active(w, true);
             RunParams r64 = single_params(w, RUN_SOLVE, w->st.max_iters, w->st.polish_iters, w->st.tol);
             r64.accumulate = 1;
+            r64.jacobi_tol = kMixedJacobiTol64;
             run_single(w, 1, r64);
             hip_check(hipMemcpyAsync(o, w->desc.out, sizeof(o), hipMemcpyDeviceToHost, w->stream), "copy");
             hip_check(hipStreamSynchronize(w->stream), "sync");
@@ -872,6 +879,9 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         B->eig_wave = (int)json_num(schedule_json, "eig_wave", 2);
         B->one_launch = (int)json_num(schedule_json, "one_launch", 1);
         B->rows_nmin = (int)json_num(schedule_json, "rows_nmin", kRowsNmin);
+        B->jacobi_tol64 = json_num(schedule_json, "fp64_jacobi_tol", kMixedJacobiTol64);
+        if (!(B->jacobi_tol64 >= 0.0 && B->jacobi_tol64 < 1e-3))
+            throw Status(SOS_E_INVAL, "schedule fp64_jacobi_tol must be in [0, 1e-3)");
         if (B->rows_nmin < 0) throw Status(SOS_E_INVAL, "schedule rows_nmin must be >= 0");
         if (B->eig_wave != 0 && B->eig_wave != 2)
             throw Status(SOS_E_INVAL, "schedule eig_wave must be 0 (lane groups) or 2 (rows over wavefronts)");
@@ -980,6 +990,7 @@ static void enqueue_batch(sos_batch *B) {
         rp.ts = B->d_ts;
         RunParams rp2 = batch_params(B, RUN_SOLVE, B->st.max_iters, B->st.polish_iters, B->st.tol);
         rp2.accumulate = 1;
+        rp2.jacobi_tol = B->jacobi_tol64;
         if (B->one_launch) {
             // both phases in one launch: each problem goes on to FP64 as soon as its own
             // FP32 phase ends

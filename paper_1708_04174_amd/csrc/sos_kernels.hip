@@ -17,6 +17,7 @@
 //            PSD part of w parked in v for the projection.
 // The identity u_hat_tau = omega_tau + theta follows from the rank-one formula:
 // zeta^T u_hat = zeta^T sigma - theta zeta^T h = zeta^T sigma / eta = theta.
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -399,50 +400,74 @@ __device__ __forceinline__ bool jacobi_rot<double>(double al, double be, double 
 }
 
 // One-sided Jacobi rotation of the column pair (p, q) of G (and of V) by a group of GS
-// lanes; makes g_p and g_q orthogonal.  Returns 0 if no rotation was applied, 1 for a
-// rotation of relative coupling at most sqrt(tol), 2 for a larger one.
-template <typename T, int GS, typename GP, typename VP>
-__device__ __forceinline__ int os_rotate_pair(GP G, int ldg, VP V, int ldv, int N, int p, int q, T tol, T atol) {
-    constexpr int RPL = 8;          // rows per lane held in registers (N <= 8 GS); larger N: streamed
+// lanes, each lane holding RPL rows of the columns in registers (N <= RPL GS).  V in global
+// memory is read up front, so that its reads are in flight during the reduction and the
+// rotation decision; V in LDS is read only once a rotation is decided (most pairs of a
+// warm-started sweep are not rotated, and LDS bandwidth is what a round spends).  Returns
+// as os_rotate_pair.
+template <typename T, int GS, int RPL, typename GP, typename VP>
+__device__ __forceinline__ int rotate_pair_regs(GP gp, GP gq, VP vp, VP vq, int N, T tol, T atol) {
+    constexpr bool kPrefetchV = !std::is_same<VP, typename Lds<T>::type *>::value;
     const int gl = threadIdx.x & (GS - 1);
-    GP gp = G + (long long)p * ldg, gq = G + (long long)q * ldg;
-    VP vp = V + (long long)p * ldv, vq = V + (long long)q * ldv;
-    T al = 0, be = 0, ga = 0;
-    if (N <= RPL * GS) {
-        // both columns of G and of V read up front: the V reads (global memory for the
-        // largest blocks) are in flight during the reduction and the rotation decision
-        T xp[RPL], xq[RPL], yp[RPL], yq[RPL];
+    T xp[RPL], xq[RPL], yp[RPL], yq[RPL];
 #pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-            const int i = gl + GS * t;
-            xp[t] = i < N ? gp[i] : (T)0;
-            xq[t] = i < N ? gq[i] : (T)0;
+    for (int t = 0; t < RPL; ++t) {
+        const int i = gl + GS * t;
+        xp[t] = i < N ? gp[i] : (T)0;
+        xq[t] = i < N ? gq[i] : (T)0;
+        if (kPrefetchV) {
             yp[t] = i < N ? vp[i] : (T)0;
             yq[t] = i < N ? vq[i] : (T)0;
         }
+    }
+    T al = 0, be = 0, ga = 0;
 #pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-            al += xp[t] * xp[t];
-            be += xq[t] * xq[t];
-            ga += xp[t] * xq[t];
-        }
-        al = group_allsum<GS>(al);
-        be = group_allsum<GS>(be);
-        ga = group_allsum<GS>(ga);
-        T cc, ss;
-        if (!jacobi_rot<T>(al, be, ga, tol * tol, atol * atol, cc, ss)) return 0;
+    for (int t = 0; t < RPL; ++t) {
+        al += xp[t] * xp[t];
+        be += xq[t] * xq[t];
+        ga += xp[t] * xq[t];
+    }
+    al = group_allsum<GS>(al);
+    be = group_allsum<GS>(be);
+    ga = group_allsum<GS>(ga);
+    T cc, ss;
+    if (!jacobi_rot<T>(al, be, ga, tol * tol, atol * atol, cc, ss)) return 0;
+    if (!kPrefetchV) {
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
             const int i = gl + GS * t;
-            if (i < N) {
-                gp[i] = cc * xp[t] - ss * xq[t];
-                gq[i] = ss * xp[t] + cc * xq[t];
-                vp[i] = cc * yp[t] - ss * yq[t];
-                vq[i] = ss * yp[t] + cc * yq[t];
-            }
+            yp[t] = i < N ? vp[i] : (T)0;
+            yq[t] = i < N ? vq[i] : (T)0;
         }
-        return ga * ga > tol * (al * be) ? 2 : 1;
     }
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+        const int i = gl + GS * t;
+        if (i < N) {
+            gp[i] = cc * xp[t] - ss * xq[t];
+            gq[i] = ss * xp[t] + cc * xq[t];
+            vp[i] = cc * yp[t] - ss * yq[t];
+            vq[i] = ss * yp[t] + cc * yq[t];
+        }
+    }
+    return ga * ga > tol * (al * be) ? 2 : 1;
+}
+
+// One-sided Jacobi rotation of the column pair (p, q) of G (and of V) by a group of GS
+// lanes; makes g_p and g_q orthogonal.  Returns 0 if no rotation was applied, 1 for a
+// rotation of relative coupling at most sqrt(tol), 2 for a larger one.  Blocks of up to
+// 16 GS rows keep the columns in registers (4, 8, 12 or 16 rows per lane, the fewest that
+// hold N); larger ones stream them.
+template <typename T, int GS, typename GP, typename VP>
+__device__ __forceinline__ int os_rotate_pair(GP G, int ldg, VP V, int ldv, int N, int p, int q, T tol, T atol) {
+    const int gl = threadIdx.x & (GS - 1);
+    GP gp = G + (long long)p * ldg, gq = G + (long long)q * ldg;
+    VP vp = V + (long long)p * ldv, vq = V + (long long)q * ldv;
+    if (N <= 4 * GS) return rotate_pair_regs<T, GS, 4>(gp, gq, vp, vq, N, tol, atol);
+    if (N <= 8 * GS) return rotate_pair_regs<T, GS, 8>(gp, gq, vp, vq, N, tol, atol);
+    if (N <= 12 * GS) return rotate_pair_regs<T, GS, 12>(gp, gq, vp, vq, N, tol, atol);
+    if (N <= 16 * GS) return rotate_pair_regs<T, GS, 16>(gp, gq, vp, vq, N, tol, atol);
+    T al = 0, be = 0, ga = 0;
     for (int i = gl; i < N; i += GS) {
         const T a = gp[i], b = gq[i];
         al += a * a;
