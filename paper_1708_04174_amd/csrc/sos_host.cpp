@@ -28,10 +28,12 @@ const int kLdsBudget = 159 * 1024;   // of the 160 KiB per workgroup, the rest f
 // (N < 32, 64, 96, 128, 192, 256, larger): 8 for 64 <= N < 128, as the autotuner picks there.
 constexpr int kRowsNmin = 96;
 // Jacobi coupling tolerance of the mixed form's FP64 phase (0: 16 eps of FP64).  That phase
-// only has to carry the iterate below the FP32 rounding floor (about 1e-7 relative), so
-// eigenvectors orthogonal to 1e-12 are ample; the sweeps stop once every coupling of a sweep
-// is under 1e-6 instead of under 6e-8.
-constexpr double kMixedJacobiTol64 = 1e-12;
+// has to carry the iterate below the FP32 floor of the affine step and of the residuals; its
+// stopping test and certificates are evaluated in FP64 on the iterate itself, whatever the
+// eigensolver's accuracy.  Eigenvectors orthogonal to 1e-7 (sweeps stop once every coupling of
+// a sweep is under 3e-4) measured as fast as FP32-level ones with the same statuses on the
+// Lyapunov batch, and save about one sweep per projection against 16 eps.
+constexpr double kMixedJacobiTol64 = 1e-7;
 constexpr int kLanesPerPair[7] = {16, 16, 8, 8, 16, 16, 16};
 // mixed form: the FP32 phase hands over after this many residual checks without a 10 % gain.
 // An FP32-stored iterate has a residual floor of about eps_32 |A| |y| / tau (above 1e-4 on the
