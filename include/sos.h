@@ -185,7 +185,9 @@ void sos_free(sos_work *w);
    for blocks that fit in LDS, 0: lane-group form for all), rows_nmin (eig_wave 2: blocks
    with N below it still take the lane-group form), lds_kb, gs_n32 .. gs_big (lanes per
    column pair of the lane-group form by block size), one_launch (mixed form: 1 runs both
-   phases in one launch, 0 in two).  Keys left out take the choice sos_solve makes with
+   phases in one launch, 0 in two), fp64_jacobi_tol (Jacobi coupling tolerance of the mixed
+   form's FP64 phase, default 1e-7; 0 = 16 eps), stall_checks (mixed form: residual checks
+   without progress before the FP64 phase, default 4).  Keys left out take the choice sos_solve makes with
    eig_form 0, so a batch without a schedule retraces single solves bitwise.  The handles
    must outlive the batch. */
 int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_json,

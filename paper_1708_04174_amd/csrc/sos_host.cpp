@@ -134,6 +134,7 @@ struct sos_batch {
     bool use_graph = true;
     int warm_eig = 1, lds_budget = 0, eig_wave = 2, rows_nmin = 0;
     double jacobi_tol64 = 0.0;   // Jacobi tolerance of the mixed form's FP64 phase
+    int stall_checks = 0;        // mixed form: checks without progress before the FP64 phase
     int one_launch = 1;   // mixed form: both phases in one launch (threads 256 or 512)
     bool used_one_launch = false;
     int gs_bucket[7] = {16, 16, 16, 16, 16, 16, 16};
@@ -882,6 +883,8 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         B->one_launch = (int)json_num(schedule_json, "one_launch", 1);
         B->rows_nmin = (int)json_num(schedule_json, "rows_nmin", kRowsNmin);
         B->jacobi_tol64 = json_num(schedule_json, "fp64_jacobi_tol", kMixedJacobiTol64);
+        B->stall_checks = (int)json_num(schedule_json, "stall_checks", kStallChecks);
+        if (B->stall_checks < 1) throw Status(SOS_E_INVAL, "schedule stall_checks must be >= 1");
         if (!(B->jacobi_tol64 >= 0.0 && B->jacobi_tol64 < 1e-3))
             throw Status(SOS_E_INVAL, "schedule fp64_jacobi_tol must be in [0, 1e-3)");
         if (B->rows_nmin < 0) throw Status(SOS_E_INVAL, "schedule rows_nmin must be >= 0");
@@ -987,7 +990,7 @@ static void enqueue_batch(sos_batch *B) {
     } else {
         // FP32 phase: to tol, or until it stops improving; then FP64 for the rest of the budget
         RunParams rp = batch_params(B, RUN_SOLVE, B->st.max_iters, 0, B->st.tol);
-        rp.stall_checks = kStallChecks;
+        rp.stall_checks = B->stall_checks;
         rp.warm_budget = B->st.warm_budget;
         rp.ts = B->d_ts;
         RunParams rp2 = batch_params(B, RUN_SOLVE, B->st.max_iters, B->st.polish_iters, B->st.tol);
