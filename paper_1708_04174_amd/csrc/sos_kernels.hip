@@ -390,12 +390,27 @@ __device__ __forceinline__ bool jacobi_rot<double>(double al, double be, double 
                                                    double &c, double &s) {
     const double g2 = ga * ga;
     if (!(g2 > tol2 * (al * be)) || !(g2 > atol2 * (al > be ? al : be))) return false;
+    // the hardware reciprocal and reciprocal square root, each refined by two Newton steps
+    // (quadratic convergence: far below 1 ulp of error left), instead of the IEEE-exact
+    // square root and divisions with their range scaling: the arguments here are positive,
+    // finite and far from the extremes
     const double d = be - al;
-    const double h = sqrt(d * d + 4.0 * g2);
-    double t = 2.0 * ga / (fabs(d) + h);
+    const double x = d * d + 4.0 * g2;   // > 0, since g2 > 0
+    double r = __builtin_amdgcn_rsq(x);
+    r = fma(0.5 * r, fma(-x * r, r, 1.0), r);
+    r = fma(0.5 * r, fma(-x * r, r, 1.0), r);
+    const double den = fabs(d) + x * r;   // |d| + sqrt(d^2 + 4 g^2)
+    double inv = __builtin_amdgcn_rcp(den);
+    inv = fma(inv, fma(-den, inv, 1.0), inv);
+    inv = fma(inv, fma(-den, inv, 1.0), inv);
+    double t = 2.0 * ga * inv;
     if (d < 0.0) t = -t;
-    c = 1.0 / sqrt(1.0 + t * t);
-    s = c * t;
+    const double y = 1.0 + t * t;
+    double cr = __builtin_amdgcn_rsq(y);
+    cr = fma(0.5 * cr, fma(-y * cr, cr, 1.0), cr);
+    cr = fma(0.5 * cr, fma(-y * cr, cr, 1.0), cr);
+    c = cr;
+    s = cr * t;
     return true;
 }
 
