@@ -300,6 +300,13 @@ __device__ __forceinline__ void rr_pair(int r, int kk, int M, int &p, int &q) {
 
 // lanes per column pair for a block of size N: the schedule's choice for N's bucket
 // (buckets N < 32, 64, 96, 128, 192, 256, and above)
+// Leading dimension of G and V when both sit in LDS: the smallest ld >= N with ld = 8 mod 16.
+// A wavefront's groups read columns p, p - 1, ..., p - 7 of one round (8 consecutive rows
+// each); with this stride the 8 column starts fall 8 banks apart modulo 64 banks (4-byte
+// elements), and 16 apart within each half-wavefront for 8-byte elements, so the groups'
+// reads of a column do not share banks.
+__host__ __device__ __forceinline__ int lds_ld(int N) { return N <= 8 ? N : ((N + 7) & ~15) + 8; }
+
 __device__ __forceinline__ int lanes_per_pair(const RunParams &rp, int N) {
     const int b = N < 32 ? 0 : N < 64 ? 1 : N < 96 ? 2 : N < 128 ? 3 : N < 192 ? 4 : N < 256 ? 5 : 6;
     const int g = rp.gs_bucket[b];
@@ -1229,9 +1236,9 @@ __device__ __noinline__ int run_phase(const ProbDesc &P, const RunParams &rp, ch
             const bool wm = rp.warm_eig && warm;
             const int gs = lanes_per_pair(rp, N);
             T *g1 = Tm + (long long)P.nmax * P.nmax, *g2 = g1 + (long long)P.nmax * P.nmax;
-            if (N <= rp.lds_nmax)        // G and V in LDS
-                project_block<T, NT>(v + off, u + off, N, vc, wm, s_mat, s_mat + (long long)N * N, ld, Tm, s_sig,
-                                     sc, rp.max_sweeps, gs);
+            if (N <= rp.lds_nmax)        // G and V in LDS, columns padded (lds_ld)
+                project_block<T, NT>(v + off, u + off, N, vc, wm, s_mat, s_mat + (long long)N * lds_ld(N), lds_ld(N),
+                                     Tm, s_sig, sc, rp.max_sweeps, gs);
             else if (N <= rp.lds_nmax_g)  // G in LDS, V in global scratch
                 project_block<T, NT>(v + off, u + off, N, vc, wm, s_mat, g1, ld, Tm, s_sig, sc, rp.max_sweeps, gs);
             else                          // both in global scratch
@@ -1460,8 +1467,8 @@ __global__ __launch_bounds__(NT) void warm_start_kernel(RunParams rp, const floa
             if (N <= rp.rows_nmax && N >= rp.rows_nmin) {
                 project_block_rows<T, NT>(blk, wx, N, nullptr, false, s_mat, Tm, sc, rp.max_sweeps);
             } else if (N <= rp.lds_nmax) {
-                project_block<T, NT>(blk, wx, N, nullptr, false, s_mat, s_mat + (long long)N * N, N, Tm, s_sig, sc,
-                                     rp.max_sweeps, lanes_per_pair(rp, N));
+                project_block<T, NT>(blk, wx, N, nullptr, false, s_mat, s_mat + (long long)N * lds_ld(N), lds_ld(N), Tm,
+                                     s_sig, sc, rp.max_sweeps, lanes_per_pair(rp, N));
             } else if (N <= rp.lds_nmax_g) {
                 project_block<T, NT>(blk, wx, N, nullptr, false, s_mat, g1, N, Tm, s_sig, sc, rp.max_sweeps,
                                      lanes_per_pair(rp, N));
@@ -1559,10 +1566,10 @@ void lds_layout(int eig_ld, int lds_budget, int nw, int &mat_off, int &lds_nmax,
     mat_off = (int)off;
     lds_nmax = lds_nmax_g = 0;
     for (int N = eig_ld; N >= 2 && !lds_nmax; --N)
-        if ((long long)(off + sizeof(T) * 2 * (size_t)N * N) <= lds_budget) lds_nmax = N;
+        if ((long long)(off + sizeof(T) * 2 * (size_t)N * lds_ld(N)) <= lds_budget) lds_nmax = N;
     for (int N = eig_ld; N >= 2 && !lds_nmax_g; --N)
         if ((long long)(off + sizeof(T) * (size_t)N * N) <= lds_budget) lds_nmax_g = N;
-    const size_t need2 = lds_nmax ? off + sizeof(T) * 2 * (size_t)lds_nmax * lds_nmax : off;
+    const size_t need2 = lds_nmax ? off + sizeof(T) * 2 * (size_t)lds_nmax * lds_ld(lds_nmax) : off;
     const size_t need1 = lds_nmax_g ? off + sizeof(T) * (size_t)lds_nmax_g * lds_nmax_g : off;
     bytes = need2 > need1 ? need2 : need1;
     // rows-per-wavefront form (eig_wave 2): G, V, partial records and sigma of one block
