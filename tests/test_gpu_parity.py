@@ -180,6 +180,44 @@ def test_setup_errors(B):
     assert e.value.code == B.SOS_E_INVAL
 
 
+def test_settings_and_schedule_errors(B):
+    prob = F.FAMILIES["c1"](0)
+    with pytest.raises(B.SosError) as e:
+        B.setup_problem(prob, B.sos_default_settings(eig_form=3))
+    assert e.value.code == B.SOS_E_INVAL
+    works = [B.setup_problem(F.pop_unconstrained(4, sd)) for sd in (0, 1)]
+    for bad in ('{"eig_wave": 1}', '{"rows_nmin": -1}', '{"stall_checks": 0}', '{"fp64_jacobi_tol": 0.01}',
+                '{"gs_n64": 12}', '{"block_threads": 96}', '{"lds_kb": 400}'):
+        with pytest.raises(B.SosError) as e:
+            B.sos_batch_setup(works, bad)
+        assert e.value.code == B.SOS_E_INVAL, bad
+    # the handles are untouched by the refused schedules
+    bt = B.sos_batch_setup(works, '{"eig_wave": 2, "rows_nmin": 0, "stall_checks": 8, "fp64_jacobi_tol": 0}')
+    infos = B.sos_batch_solve(bt)
+    assert all(i["status"] == B.SOS_SOLVED for i in infos)
+    bt.free()
+
+
+def test_batch_queue_stamps(B):
+    # each problem's queue start and finish lie inside the launch, start <= finish; single
+    # solves report zeros
+    probs = [F.pop_unconstrained(n, sd) for n, sd in ((4, 0), (5, 1), (6, 2))] + [F.FAMILIES["c5"](2)]
+    s = B.sos_default_settings(precision=B.SOS_FP32_MIXED, polish_iters=1)
+    works = [B.setup_problem(p, s) for p in probs]
+    bt = B.sos_batch_setup(works, '{"use_graph": 0}')
+    infos = B.sos_batch_solve(bt)
+    launch = B.sos_batch_phase_ms(bt, 0)
+    for inf in infos:
+        print(f"[stamps] start {inf['start_ms']:.3f} end {inf['end_ms']:.3f} launch {launch:.3f}", flush=True)
+        assert 0.0 <= inf["start_ms"] <= inf["end_ms"] <= launch + 1e-6
+    assert min(i["start_ms"] for i in infos) < 1.0
+    bt.free()
+    w = B.setup_problem(probs[0], s)
+    inf = B.sos_solve(w)
+    assert inf["start_ms"] == 0.0 and inf["end_ms"] == 0.0
+    w.free()
+
+
 def test_batch_fp64_equals_single_solves(B):
     # one persistent launch over uneven problems gives the same iterates as one launch per problem
     probs = [F.pop_unconstrained(n, sd) for n, sd in ((4, 0), (5, 1), (6, 2), (7, 3), (8, 4))]
