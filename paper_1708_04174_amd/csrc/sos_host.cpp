@@ -453,6 +453,7 @@ void build(sos_work *w, const sos_csc *A, const double *b, const double *c, cons
     P.colval64 = up_d(colval);
     P.colval32 = up_f(colval);
     P.fptr = up_i(fptr);
+    P.fcol = up_i(fcols);
     P.frow = up_i(frow);
     P.fval64 = up_d(fval);
     P.fval32 = up_f(fval);

@@ -32,6 +32,7 @@ struct ProbDesc {
     const double *colval64; const float *colval32;
     // A_f in CSC (k columns) and CSR (rows -> A_f column index)
     const int *fptr, *frow;
+    const int *fcol;                 // A_f column j is internal column fcol[j]
     const double *fval64; const float *fval32;
     const int *frptr, *frcol;
     const double *frval64; const float *frval32;

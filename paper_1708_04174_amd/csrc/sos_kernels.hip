@@ -131,8 +131,21 @@ __device__ __forceinline__ void schur_solve(const double *__restrict__ Sinv, int
         const int i = t % kp, sg = t / kp;
         double acc = 0.0;
         if (i < k) {
+            // eight loads of S^{-1} in flight at a time, four partial sums
             const int j0 = sg * k / nseg, j1 = (sg + 1) * k / nseg;
-            for (int j = j0; j < j1; ++j) acc += Sinv[(long long)j * k + i] * z[j];
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int j = j0;
+            for (; j + 8 <= j1; j += 8) {
+                double sv[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) sv[q] = Sinv[(long long)(j + q) * k + i];
+                a0 += sv[0] * z[j] + sv[4] * z[j + 4];
+                a1 += sv[1] * z[j + 1] + sv[5] * z[j + 5];
+                a2 += sv[2] * z[j + 2] + sv[6] * z[j + 6];
+                a3 += sv[3] * z[j + 3] + sv[7] * z[j + 7];
+            }
+            for (; j < j1; ++j) a0 += Sinv[(long long)j * k + i] * z[j];
+            acc = (a0 + a1) + (a2 + a3);
         }
         part[t] = acc;   // t < kp nseg <= max(kp, NT) <= 1024
     }
@@ -142,6 +155,32 @@ __device__ __forceinline__ void schur_solve(const double *__restrict__ Sinv, int
         for (int sg = 0; sg < nseg; ++sg) s += part[sg * kp + i];
         z[i] = s;
     }
+}
+
+// Cross-lane moves within rows of 16 lanes (DPP, no LDS round trip).
+enum { DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_ROW_MIRROR = 0x140, DPP_HALF_MIRROR = 0x141 };
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over an aligned group of GS (8, 16 or 32) lanes.  Each step adds a lane's partial sum
+// to its partner's, partners swapping roles; since a + b == b + a exactly, every lane of
+// the group ends with the bitwise-same total, so branches on it stay uniform in the group.
+template <int GS, typename T>
+__device__ __forceinline__ T group_allsum(T x) {
+    x += dpp_mov<DPP_XOR1>(x);
+    x += dpp_mov<DPP_XOR2>(x);
+    x += dpp_mov<DPP_HALF_MIRROR>(x);
+    if constexpr (GS >= 16) x += dpp_mov<DPP_ROW_MIRROR>(x);
+    if constexpr (GS >= 32) x += __shfl_xor(x, 16, 64);
+    return x;
 }
 
 // ----------------------------------------------------------------------------- affine step
@@ -174,27 +213,41 @@ __device__ __noinline__ void affine_phase(const ProbDesc &P, const RunParams &rp
     const AT wt = (AT)wtau;
     const T *__restrict__ uy = u + nx;
 
-    // P1: x = (w2 - A w1) / d
+    // P1: x = (w2 - A w1) / d.  A row has up to a few tens of nonzeros, each a chain of two
+    // dependent loads (column index, then u, v, c there): four entries in flight at a time
     for (int a = tid; a < m; a += NT) {
         AT acc = (AT)uy[a] + (AT)b[a] * wt;
+        AT acc1 = (AT)0, acc2 = (AT)0, acc3 = (AT)0;
         const int e1 = rowptr[a + 1];
-        for (int e = rowptr[a]; e < e1; ++e) {
+        int e = rowptr[a];
+        for (; e + 4 <= e1; e += 4) {
+            const int j0 = colidx[e], j1 = colidx[e + 1], j2 = colidx[e + 2], j3 = colidx[e + 3];
+            acc -= (AT)val[e] * ((AT)u[j0] + (AT)v[j0] - (AT)c[j0] * wt);
+            acc1 -= (AT)val[e + 1] * ((AT)u[j1] + (AT)v[j1] - (AT)c[j1] * wt);
+            acc2 -= (AT)val[e + 2] * ((AT)u[j2] + (AT)v[j2] - (AT)c[j2] * wt);
+            acc3 -= (AT)val[e + 3] * ((AT)u[j3] + (AT)v[j3] - (AT)c[j3] * wt);
+        }
+        for (; e < e1; ++e) {
             const int j = colidx[e];
             acc -= (AT)val[e] * ((AT)u[j] + (AT)v[j] - (AT)c[j] * wt);
         }
-        wy[a] = acc * (AT)dinv[a];
+        wy[a] = (acc + acc1 + (acc2 + acc3)) * (AT)dinv[a];
     }
     __syncthreads();
 
-    // P2: q = A_f^T x, then z = S^{-1} q in FP64
+    // P2: q = A_f^T x, then z = S^{-1} q in FP64.  A column of A_f has a few nonzeros, so a
+    // group of 8 lanes takes one column (DPP reduction within the group) and NT / 8 columns
+    // are in flight at once: each column is a chain of dependent loads (fptr, frow, x)
     if (k > 0) {
         const int *__restrict__ fptr = P.fptr;
         const int *__restrict__ frow = P.frow;
-        for (int j = wid; j < k; j += NW) {
+        const int grp = tid >> 3, gl = tid & 7;
+        for (int j = grp; j < k; j += NT / 8) {
             double s = 0.0;
-            for (int e = fptr[j] + lane; e < fptr[j + 1]; e += 64) s += (double)fval[e] * (double)wy[frow[e]];
-            s = wave_sum(s);
-            if (lane == 0) s_z[j] = s;
+            const int e1 = fptr[j + 1];
+            for (int e = fptr[j] + gl; e < e1; e += 8) s += (double)fval[e] * (double)wy[frow[e]];
+            s = group_allsum<8>(s);
+            if (gl == 0) s_z[j] = s;
         }
         __syncthreads();
         schur_solve<NT>(P.Sinv, k, s_z, s_z + SOS_KMAX_LDS);
@@ -209,9 +262,17 @@ __device__ __noinline__ void affine_phase(const ProbDesc &P, const RunParams &rp
         for (int a = tid; a < m; a += NT) {
             AT s2 = wy[a];
             if (k > 0) {
-                double acc = 0.0;
-                for (int e = frptr[a]; e < frptr[a + 1]; ++e) acc += (double)frval[e] * s_z[frcol[e]];
-                s2 = s2 - (AT)(acc * (double)dinv[a]);
+                double acc = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+                const int e1 = frptr[a + 1];
+                int e = frptr[a];
+                for (; e + 4 <= e1; e += 4) {
+                    acc += (double)frval[e] * s_z[frcol[e]];
+                    acc1 += (double)frval[e + 1] * s_z[frcol[e + 1]];
+                    acc2 += (double)frval[e + 2] * s_z[frcol[e + 2]];
+                    acc3 += (double)frval[e + 3] * s_z[frcol[e + 3]];
+                }
+                for (; e < e1; ++e) acc += (double)frval[e] * s_z[frcol[e]];
+                s2 = s2 - (AT)(((acc + acc1) + (acc2 + acc3)) * (double)dinv[a]);
             }
             wy[a] = s2;
             bs += (double)b[a] * (double)s2;
@@ -219,25 +280,33 @@ __device__ __noinline__ void affine_phase(const ProbDesc &P, const RunParams &rp
     }
     __syncthreads();
 
-    // P4: sigma_1 = w1 + A^T sigma_2 ; partial c^T sigma_1
+    // P4: sigma_1 = w1 + A^T sigma_2 ; partial c^T sigma_1.  Columns with at most one nonzero
+    // (A_s, empty) one per thread; the columns of A_f a group of 8 lanes each (as in P2)
     double cs = 0.0;
     {
-        const int *__restrict__ fptr = P.fptr;
-        const int *__restrict__ frow = P.frow;
         for (int e = tid; e < nx; e += NT) {
-            const AT w1 = (AT)u[e] + (AT)v[e] - (AT)c[e] * wt;
             const int r = colrow[e];
-            AT s1 = w1;
-            if (r >= 0) {
-                s1 = w1 + (AT)colval[e] * wy[r];
-            } else if (r <= -2) {
-                const int j = -2 - r;
-                AT acc = (AT)0;
-                for (int i = fptr[j]; i < fptr[j + 1]; ++i) acc += (AT)fval[i] * wy[frow[i]];
-                s1 = w1 + acc;
-            }
+            if (r <= -2) continue;
+            const AT w1 = (AT)u[e] + (AT)v[e] - (AT)c[e] * wt;
+            const AT s1 = r >= 0 ? w1 + (AT)colval[e] * wy[r] : w1;
             wx[e] = s1;
             cs += (double)cw[e] * (double)s1;
+        }
+        const int *__restrict__ fptr = P.fptr;
+        const int *__restrict__ frow = P.frow;
+        const int *__restrict__ fcol = P.fcol;
+        const int grp = tid >> 3, gl = tid & 7;
+        for (int j = grp; j < k; j += NT / 8) {
+            AT acc = (AT)0;
+            const int i1 = fptr[j + 1];
+            for (int i = fptr[j] + gl; i < i1; i += 8) acc += (AT)fval[i] * wy[frow[i]];
+            acc = group_allsum<8>(acc);
+            if (gl == 0) {
+                const int e = fcol[j];
+                const AT s1 = (AT)u[e] + (AT)v[e] - (AT)c[e] * wt + acc;
+                wx[e] = s1;
+                cs += (double)cw[e] * (double)s1;
+            }
         }
     }
     block_sum2<NT>(cs, bs, s_red);
@@ -333,34 +402,6 @@ __device__ __forceinline__ double wave_allsum(double x) {
 __device__ __forceinline__ float wave_allsum(float x) {
     for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
     return __shfl(x, 0, 64);
-}
-
-// Sum over a group of GS consecutive lanes; every lane of the group gets the group's first
-// lane's result, so branches on it are uniform inside the group.
-// Cross-lane moves within rows of 16 lanes (DPP, no LDS round trip).
-enum { DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_ROW_MIRROR = 0x140, DPP_HALF_MIRROR = 0x141 };
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double x) {
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-// Sum over an aligned group of GS (8, 16 or 32) lanes.  Each step adds a lane's partial sum
-// to its partner's, partners swapping roles; since a + b == b + a exactly, every lane of
-// the group ends with the bitwise-same total, so branches on it stay uniform in the group.
-template <int GS, typename T>
-__device__ __forceinline__ T group_allsum(T x) {
-    x += dpp_mov<DPP_XOR1>(x);
-    x += dpp_mov<DPP_XOR2>(x);
-    x += dpp_mov<DPP_HALF_MIRROR>(x);
-    if constexpr (GS >= 16) x += dpp_mov<DPP_ROW_MIRROR>(x);
-    if constexpr (GS >= 32) x += __shfl_xor(x, 16, 64);
-    return x;
 }
 
 // Absolute floor of the coupling a pair must have to be rotated, in units of eps |W|_F
