@@ -580,27 +580,81 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
         __syncthreads();
         return;
     }
-    // G = W (cold, V = I) or G = W V_prev (warm); W is symmetric, so column j of W = row j
+    // G = W (cold, V = I) or G = W V_prev (warm); W is symmetric, so column j of W = row j.
+    // Warm, with at most one 4 x 4 tile of G per thread, W is staged where G goes and each
+    // thread keeps its tile of W V in registers until every read of W is done; otherwise W
+    // is staged in the global scratch Tm.
+    const int nt = (N + 3) >> 2;
+    const bool wreg = warm && nt * nt <= NT;
+    // four entries per thread and pass, their global reads issued together
     double fro2 = 0.0, dummy = 0.0;
-    for (int idx = tid; idx < N * N; idx += NT) {
-        const int j = idx / N, i = idx - (idx / N) * N;   // column j, row i
-        const int a = i > j ? i : j, bb = i > j ? j : i;
-        const T x = vs[svec_idx(a, bb, N)];
-        fro2 += (double)x * (double)x;
-        if (warm) {
-            Tm[j * N + i] = x;
-            V[j * ld + i] = Vs[j * N + i];
-        } else {
-            G[j * ld + i] = x;
-            V[j * ld + i] = (i == j) ? (T)1 : (T)0;
+    for (int base = 0; base < N * N; base += 4 * NT) {
+        int ii[4], jj[4];
+        T xs[4], vv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = base + q * NT + tid;
+            jj[q] = idx / N;
+            ii[q] = idx - jj[q] * N;   // column jj, row ii
+            if (idx < N * N) {
+                const int a = ii[q] > jj[q] ? ii[q] : jj[q], bb = ii[q] > jj[q] ? jj[q] : ii[q];
+                xs[q] = vs[svec_idx(a, bb, N)];
+                vv[q] = warm ? Vs[jj[q] * N + ii[q]] : (ii[q] == jj[q] ? (T)1 : (T)0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (base + q * NT + tid >= N * N) continue;
+            const int i = ii[q], j = jj[q];
+            const T x = xs[q];
+            fro2 += (double)x * (double)x;
+            if (warm && !wreg)
+                Tm[j * N + i] = x;
+            else
+                G[j * ld + i] = x;
+            V[j * ld + i] = vv[q];
         }
     }
     __syncthreads();
-    if (warm) {
+    if (wreg) {
+        // G[:, j] = sum_k W[:, k] V[k, j], one tile per thread, W read from G's storage.
+        // Consecutive threads take consecutive row tiles of one column tile: a wavefront then
+        // reads a few columns of V (broadcast) and consecutive rows of W, where column tiles
+        // at stride ld would put its V reads in a couple of banks
+        const bool act = tid < nt * nt;
+        const int j0 = (tid / nt) * 4, i0 = (tid - (tid / nt) * nt) * 4;
+        T acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+        if (act) {
+#pragma unroll 4
+            for (int kk = 0; kk < N; ++kk) {
+                T wa[4], vb[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) wa[a] = (i0 + a < N) ? G[kk * ld + i0 + a] : (T)0;   // W[i][k]
+#pragma unroll
+                for (int b = 0; b < 4; ++b) vb[b] = (j0 + b < N) ? V[(j0 + b) * ld + kk] : (T)0;   // V[k][j]
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] += wa[a] * vb[b];
+            }
+        }
+        __syncthreads();   // every read of W done before G overwrites it
+        if (act) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (i0 + a < N && j0 + b < N) G[(j0 + b) * ld + i0 + a] = acc[a][b];
+        }
+        __syncthreads();
+    } else if (warm) {
         // G[:, j] = sum_k W[:, k] V[k, j]  (column-major: G^T = V^T W^T, computed as (V^T W)^T)
-        const int nt = (N + 3) >> 2;
         for (int t = tid; t < nt * nt; t += NT) {
-            const int i0 = (t / nt) * 4, j0 = (t - (t / nt) * nt) * 4;
+            const int j0 = (t / nt) * 4, i0 = (t - (t / nt) * nt) * 4;   // row tiles fastest (bank spread)
             T acc[4][4];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
@@ -693,7 +747,6 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
     }
     __syncthreads();
     // u = lower((W + V Sigma V^T) / 2), v = u - w, by 4 x 4 tiles on and below the diagonal
-    const int nt = (N + 3) >> 2;
     const int ntri = nt * (nt + 1) / 2;
     for (int t = tid; t < ntri; t += NT) {
         int ta = 0, rem = t;
@@ -868,7 +921,7 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
         // G = W V_prev, 4 x 4 tiles over the workgroup
         const int nt = (N + 3) >> 2;
         for (int t = tid; t < nt * nt; t += NT) {
-            const int i0 = (t / nt) * 4, j0 = (t - (t / nt) * nt) * 4;
+            const int j0 = (t / nt) * 4, i0 = (t - (t / nt) * nt) * 4;   // row tiles fastest (bank spread)
             T acc[4][4];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
