@@ -760,6 +760,8 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+        // four columns of V per step: their LDS reads are in flight together
+#pragma unroll 4
         for (int j = 0; j < N; ++j) {
             const T sg = s_sig[j];
             T va[4], vb[4];
@@ -1152,6 +1154,7 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+#pragma unroll 4
         for (int j = 0; j < N; ++j) {
             const T sg = sig[j];
             T va[4], vb[4];
