@@ -141,8 +141,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: a batch would be split across GPUs by problem "
-                                   "(see the design notes), which is not part of it", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "bench.py measures one GPU: a batch would be split across GPUs by problem, "
+                                   "which is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch

@@ -24,7 +24,7 @@ What it computes (Zheng, Fantuzzi, Papachristodoulou, arXiv 1708.04174):
 * The PSD projection uses LAPACK eigh on the symmetrised block, clamps the
   eigenvalues at zero and rebuilds V max(L, 0) V^T.
 
-Readings where the paper is silent (each also listed in the design notes):
+Readings where the paper is silent:
 * start point u = v = (0, 0, 1), as in the ADMM paper the method builds on;
 * relaxation alpha = 1 (the paper's three steps have none);
 * stopping: max(r_p, r_d, r_g) <= tol with the normalised residuals below,
