@@ -214,7 +214,11 @@ def test_lyapunov_unperturbed_is_feasible():
 @pytest.mark.parametrize("n", [4, 6, 10])
 def test_example_pop_matches_brute_force_and_table3(n):
     # Section VII-A polynomial on the unit ball: the order-2 relaxation is tight here, so gamma*
-    # equals the brute-force minimum; Table III's interior-point value agrees to 0.25 %.
+    # equals the brute-force minimum of the printed polynomial.  That is the pin.  Table III's
+    # interior-point values cannot pin it to their two printed decimals: the printed polynomial's
+    # minimum on the ball lies below them (n = 10: -9.1278 against -9.11; n = 12: -11.1273
+    # against -11.12; n = 14: -13.1269 against -13.12), by more than the rounding of the print,
+    # so only agreement within 0.02, with the oracle below the printed value, is checked there.
     prob = F.example_pop(n)
     r = Oracle.from_problem(prob).solve(tol=1e-7, max_iters=50000)
     assert r.status == SOLVED
@@ -226,7 +230,8 @@ def test_example_pop_matches_brute_force_and_table3(n):
     assert abs(gamma - ref) <= 2e-5 * abs(ref)
     assert gamma <= -(n - 1)                       # p(e_n) = -(n-1)
     if str(n) in GOLD["ipm_gamma"]:
-        assert abs(gamma - GOLD["ipm_gamma"][str(n)]) <= 2.5e-3 * abs(gamma)
+        printed = GOLD["ipm_gamma"][str(n)]
+        assert printed - 0.02 <= gamma < printed
 
 
 # ---------------------------------------------------------------- planted mistakes
