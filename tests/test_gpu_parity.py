@@ -1,9 +1,18 @@
 """GPU parity: the gfx950 library against the FP64 CPU oracle, through the C ABI.
 
-Bar (FP64 form): iterates after k identical steps agree to 1e-9 relative (both are
-exact up to rounding, and one ADMM step is nonexpansive, so rounding does not grow);
-solved objective values agree to 1e-6 relative.
+Bars.  Iterates are compared entry by entry: max_i |gpu_i - ref_i| / max(1, |ref_i|).
+* FP64 form: iterates after k identical steps within 1e-9 (both are exact up to rounding,
+  and one ADMM step is nonexpansive, so rounding does not grow); solved objective values
+  within 1e-6 relative.
+* FP32 bulk (SOS_FP32_MIXED, sos_step): every step rounds the iterate to FP32 and the
+  eigensolver stops at a relative coupling of 16 eps_32, so each step adds an error of a few
+  hundred eps_32 times the size of the iterate; the map is nonexpansive, so after k steps the
+  entries are within k * FP32_STEP_ERR * max(1, |ref|_inf) of the oracle.
+* Mixed-precision solves: gamma within 5 tol relative of the FP64 oracle, and the same status.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -13,6 +22,10 @@ from sosgen import families as F
 pytestmark = pytest.mark.gpu
 
 ITER_RTOL = 1e-9
+# per-step error allowance of the FP32 bulk form, in units of the iterate's largest entry:
+# 512 eps_32 (eps_32 = 1.19e-7)
+FP32_STEP_ERR = 512 * 1.1920929e-07
+TABLES = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_tables.json")))
 
 
 @pytest.fixture(scope="module")
@@ -24,11 +37,12 @@ def B():
     return binding
 
 
-def _rel(a, b):
-    return np.linalg.norm(a - b) / max(1.0, np.linalg.norm(b))
+def _elem(a, b):
+    """max_i |a_i - b_i| / max(1, |b_i|)."""
+    return float(np.max(np.abs(a - b) / np.maximum(1.0, np.abs(b)))) if len(b) else 0.0
 
 
-def _step_parity(B, prob, ks, settings=None, tag=""):
+def _step_parity(B, prob, ks, settings=None, tag="", fp32=False):
     o = Oracle.from_problem(prob)
     w = B.setup_problem(prob, settings)
     u, v = o.initial()
@@ -38,9 +52,17 @@ def _step_parity(B, prob, ks, settings=None, tag=""):
         u, v = o.run(k - done, u, v)
         done = k
         ug, vg = B.sos_get_iterate(w)
-        eu, ev = _rel(ug, u), _rel(vg, v)
-        print(f"[parity] {tag} k={k} |du|={eu:.2e} |dv|={ev:.2e}", flush=True)
-        assert eu <= ITER_RTOL and ev <= ITER_RTOL, (tag, k, eu, ev)
+        if fp32:
+            # entries relative to the iterate's largest entry (FP32 rounding is relative to it)
+            scale = max(1.0, float(np.max(np.abs(u))), float(np.max(np.abs(v))))
+            eu = float(np.max(np.abs(ug - u))) / scale
+            ev = float(np.max(np.abs(vg - v))) / scale
+            bound = k * FP32_STEP_ERR
+        else:
+            eu, ev = _elem(ug, u), _elem(vg, v)
+            bound = ITER_RTOL
+        print(f"[parity] {tag} k={k} |du|={eu:.2e} |dv|={ev:.2e} bound {bound:.1e}", flush=True)
+        assert eu <= bound and ev <= bound, (tag, k, eu, ev)
     w.free()
 
 
@@ -89,6 +111,84 @@ def test_step_parity_c3_full_size(B):
 def test_step_parity_c2_full_size(B):
     # unconstrained quartic POP, n = 20: Gram block 231, m = 10626
     _step_parity(B, F.FAMILIES["c2"](0), [1, 2], tag="c2_full")
+
+
+FP32_CASES = {
+    "c1_seed0": lambda: F.FAMILIES["c1"](0),
+    "ball_n3_weighted": lambda: F.pop_ball(3, 2),
+    "lyapunov_c5_seed0": lambda: F.FAMILIES["c5"](0),
+    "lyapunov_c5_seed3610": lambda: F.FAMILIES["c5"](3610),
+    "pop_n10": lambda: F.pop_unconstrained(10, 3),
+    "ball_c3_full": lambda: F.FAMILIES["c3"](0),
+}
+
+
+@pytest.mark.parametrize("name", list(FP32_CASES))
+def test_step_parity_fp32_bulk(B, name):
+    # the FP32 kernels (affine step and eigensolvers in FP32, FP64 small solve, theta and
+    # tau / kappa) step by step against the FP64 oracle, at the C5 (blocks 28 + 84, k = 203)
+    # and C3 (blocks 153 + 17, k = 154) shapes among others
+    s = B.sos_default_settings(precision=B.SOS_FP32_MIXED)
+    _step_parity(B, FP32_CASES[name](), [1, 3, 10, 30], settings=s, tag=f"fp32_{name}", fp32=True)
+
+
+def test_c2_status_matches_the_oracle(B):
+    # the n = 20 POP with N(0, 0.1) quartic cross terms is unbounded below, so max gamma is
+    # primal infeasible: the FP64 GPU solve must end with the certificate the oracle gives
+    ref = TABLES["pop_n20"]["seeds"]["0"]
+    w = B.setup_problem(F.FAMILIES["c2"](0), B.sos_default_settings(tol=1e-4, max_iters=2000))
+    info = B.sos_solve(w)
+    print(f"[c2] gpu {info['status_name']} after {info['iters']} (oracle status {ref['status']} after "
+          f"{ref['iters']}), {info['solve_ms']:.0f} ms, {info['solve_ms'] / max(1, info['iters']):.3f} ms/iter",
+          flush=True)
+    assert info["status"] == ref["status"] == B.SOS_PRIMAL_INFEASIBLE
+    assert abs(info["iters"] - ref["iters"]) <= 20
+    w.free()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_c3_mixed_precision_gamma_error(B, seed):
+    # constrained quartic POP on the unit ball, n = 16 (blocks 153 and 17, m = 4845, k = 154),
+    # FP32 bulk / FP64 islands and polish, against the oracle's gamma at tol 1e-7
+    ref = TABLES["ball_pop_n16"]["seeds"][str(seed)]
+    s = B.sos_default_settings(tol=1e-4, max_iters=2000, precision=B.SOS_FP32_MIXED, polish_iters=1)
+    w = B.setup_problem(F.FAMILIES["c3"](seed), s)
+    info = B.sos_solve(w)
+    x, _, _ = B.sos_get_solution(w)
+    g_ref = ref["reference"]["gamma"]
+    err = abs(x[0] - g_ref) / max(1.0, abs(g_ref))
+    res = max(info["res_pri"], info["res_dual"], info["gap"])
+    print(f"[c3] seed {seed}: {info['status_name']} in {info['iters']} iterations ({info['polish_iters']} FP64), "
+          f"gamma {x[0]:.6f} vs oracle {g_ref:.6f}: error {err:.2e} (bound 5e-4); res {res:.1e}; "
+          f"oracle at 1e-4: status {ref['tol_1e-4']['status']} in {ref['tol_1e-4']['iters']}; "
+          f"{info['solve_ms']:.0f} ms", flush=True)
+    assert info["status"] == B.SOS_SOLVED == ref["tol_1e-4"]["status"] and res <= 1e-4
+    assert err <= 5e-4
+    w.free()
+
+
+def test_c5_statuses_match_the_oracle(B):
+    # the benchmark's Lyapunov programs, batched in the mixed form from the cold start: the
+    # status of each (solved, primal infeasible, iteration cap) equals the oracle's, on a slice
+    # that holds infeasible instances (3610, 3611) and iteration-cap ones
+    table = TABLES["lyapunov_512"]["seeds"]
+    seeds = list(range(3600, 3664))
+    s = B.sos_default_settings(tol=1e-4, max_iters=2000, precision=B.SOS_FP32_MIXED, polish_iters=1)
+    works = [B.setup_problem(F.lyapunov(sd), s) for sd in seeds]
+    bt = B.sos_batch_setup(works)
+    infos = B.sos_batch_solve(bt)
+    bad = []
+    for sd, inf in zip(seeds, infos):
+        ref = table[str(sd)]
+        if inf["status"] != ref["status"]:
+            bad.append((sd, inf["status_name"], inf["iters"], ref["status"], ref["iters"]))
+    counts = {}
+    for inf in infos:
+        counts[inf["status_name"]] = counts.get(inf["status_name"], 0) + 1
+    print(f"[c5] statuses {counts}; disagreements with the oracle: {bad}", flush=True)
+    assert {table[str(sd)]["status"] for sd in seeds} >= {1, 2}
+    assert not bad
+    bt.free()
 
 
 CLOSED = [
@@ -149,7 +249,7 @@ def test_checkpoint_resume(B):
     assert np.array_equal(u_back, u_mid) and np.array_equal(v_back, v_mid)
     B.sos_step(w2, 23)
     u2, v2 = B.sos_get_iterate(w2)
-    assert _rel(u2, u_ref) <= 1e-12 and _rel(v2, v_ref) <= 1e-12
+    assert _elem(u2, u_ref) <= 1e-12 and _elem(v2, v_ref) <= 1e-12
 
 
 def test_repeat_runs_are_bitwise_equal(B):
@@ -246,21 +346,30 @@ def test_batch_fp64_equals_single_solves(B):
 
 
 def test_batch_mixed_precision_gamma_error(B):
-    # FP32 bulk + FP64 polish: gamma error against the FP64 oracle, stated per problem
-    probs = [F.pop_unconstrained(n, sd) for n, sd in ((4, 0), (4, 1), (4, 3), (5, 4))] + [F.pop_ball(3, 5)]
+    # FP32 bulk + FP64 polish: the status equals the oracle's at the same tolerance and
+    # iteration budget, and a solved gamma is within 5 tol of the oracle's tol 1e-7 value.
+    # The n = 6 and n = 7 POPs (seeds 5, 6) sit at the edge of SOS feasibility: the oracle
+    # itself does not reach 1e-4 within the budget, and neither does the GPU
+    probs = [F.pop_unconstrained(n, sd) for n, sd in ((4, 0), (4, 1), (4, 3), (5, 4), (6, 5), (7, 6))]
+    probs += [F.pop_ball(3, 5)]
     s = B.sos_default_settings(tol=1e-4, max_iters=4000, precision=B.SOS_FP32_MIXED, polish_iters=1)
     works = [B.setup_problem(p, s) for p in probs]
     bt = B.sos_batch_setup(works)
     infos = B.sos_batch_solve(bt)
     for p, inf, w in zip(probs, infos, works):
-        r = Oracle.from_problem(p).solve(tol=1e-7, max_iters=30000)
-        x, _, _ = B.sos_get_solution(w)
-        err = abs(x[0] - r.x[0]) / max(1.0, abs(r.x[0]))
+        o = Oracle.from_problem(p)
+        same = o.solve(tol=1e-4, max_iters=4000)
         res = max(inf["res_pri"], inf["res_dual"], inf["gap"])
-        print(f"[mixed] N={p.psd_dims} status={inf['status_name']} iters={inf['iters']} "
-              f"(fp64 {inf['polish_iters']}) gamma err {err:.2e} res {res:.1e}", flush=True)
-        assert inf["status"] == B.SOS_SOLVED and res <= 1e-4
-        assert err <= 5e-4
+        line = (f"[mixed] N={p.psd_dims} status={inf['status_name']} iters={inf['iters']} "
+                f"(fp64 {inf['polish_iters']}) res {res:.1e}; oracle {same.status_name} in {same.iters}")
+        assert inf["status"] == same.status, line
+        if same.status == 1:
+            r = o.solve(tol=1e-7, max_iters=30000)
+            x, _, _ = B.sos_get_solution(w)
+            err = abs(x[0] - r.x[0]) / max(1.0, abs(r.x[0]))
+            line += f"; gamma err {err:.2e}"
+            assert res <= 1e-4 and err <= 5e-4, line
+        print(line, flush=True)
     bt.free()
 
 

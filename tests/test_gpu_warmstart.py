@@ -34,16 +34,22 @@ def test_mlp_gradient_matches_reference(env, dims, batch):
     net.set_params(theta)
     g, L = net.gradient(_dev(torch, X), _dev(torch, T))
     gr, Lr = ref.gradient(theta.astype(np.float64), X, T, dims)
-    err = np.linalg.norm(g - gr) / np.linalg.norm(gr)
-    print(f"[mlp] dims={dims} batch={batch} grad rel err {err:.2e} loss {L:.6f} vs {Lr:.6f}", flush=True)
-    assert err < 2e-5 and abs(L - Lr) <= 1e-5 * Lr
+    # entry by entry, |g_i - r_i| / max(1, |r_i|): FP32 sums of batch x width products, each
+    # with a relative rounding error of a few eps_32 (1.2e-7), entries of order 1e-2 at most
+    err = float(np.max(np.abs(g - gr) / np.maximum(1.0, np.abs(gr))))
+    print(f"[mlp] dims={dims} batch={batch} grad max entry err {err:.2e} (max |g| {np.max(np.abs(gr)):.1e}) "
+          f"loss {L:.6f} vs {Lr:.6f}", flush=True)
+    assert err < 1e-6 and abs(L - Lr) <= 1e-5 * Lr
     # forward with the output affine
     Y = torch.empty((batch, dims[2]), dtype=torch.float32, device="cuda")
     sc, sh = rng.uniform(0.5, 2, dims[2]), rng.standard_normal(dims[2])
     net.set_output_affine(sc, sh)
     net.forward(_dev(torch, X), Y, apply_output_affine=True)
     Yr, _ = ref.forward(theta.astype(np.float64), X, dims)
-    assert np.allclose(Y.cpu().numpy(), Yr * sc + sh, rtol=1e-4, atol=1e-4)
+    Yw = Yr * sc + sh
+    yerr = float(np.max(np.abs(Y.cpu().numpy() - Yw) / np.maximum(1.0, np.abs(Yw))))
+    print(f"[mlp] forward max entry err {yerr:.2e}", flush=True)
+    assert yerr < 1e-4
     net.free()
 
 
