@@ -148,6 +148,19 @@ int sos_setup(const sos_csc *A, const double *b, const double *c, const sos_cone
    the stream has finished.  iters >= 0.  info may be NULL. */
 int sos_step(sos_work *w, int32_t iters, sos_info *info);
 
+/* sos_step for callers that cannot allocate device memory (code under HIP graph capture,
+   tight serving loops, harnesses that forbid hipMalloc): the same iterations, kernels and
+   results as sos_step, but the launch's scratch (queue counter, affine work vector,
+   eigensolver area) lives in a static device array of 4 MiB that the library holds on each
+   GPU it runs on until the process ends, instead of the handle's own.  No hipMalloc, hipFree
+   or other allocating call is made; the handle's device must be current.  The array keeps
+   the last call's contents; each call clears what must start at zero (the queue counter)
+   with a kernel, and every other byte is written before it is read.  Calls that overlap on
+   one GPU share the array and race: serialise them (one stream, or host ordering).
+   A problem needing more than 4 MiB of scratch (about 3 N^2 + m + n_x doubles, N the
+   largest block) is rejected with SOS_E_INVAL and a message; then nothing is launched. */
+int sos_step_static(sos_work *w, int32_t iters, sos_info *info);
+
 /* Iterates from the current state until a stopping test holds or max_iters; in
    SOS_FP32_MIXED form the FP32 phase is followed by FP64 iterations (at least
    polish_iters) until the FP64 residuals meet tol.  Blocks until done. */

@@ -22,7 +22,7 @@ SOS_FP64, SOS_FP32_MIXED = 0, 1
 SOS_PART_PAPER, SOS_PART_COLUMNS = 0, 1
 STATUS_NAMES = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_infeasible", 4: "max_iters"}
 
-EXPORTED = ["sos_default_settings", "sos_setup", "sos_step", "sos_solve", "sos_warm_start",
+EXPORTED = ["sos_default_settings", "sos_setup", "sos_step", "sos_step_static", "sos_solve", "sos_warm_start",
             "sos_get_solution", "sos_get_iterate", "sos_set_iterate", "sos_last_error", "sos_free",
             "sos_batch_setup", "sos_batch_solve", "sos_batch_reset", "sos_batch_last_ms",
             "sos_batch_phase_ms", "sos_batch_free", "sos_layout_size", "sos_batch_warm_start",
@@ -89,6 +89,7 @@ def load():
     lib.sos_default_settings.argtypes = [P(sos_settings)]
     lib.sos_setup.argtypes = [P(sos_csc), P(C.c_double), P(C.c_double), P(sos_cone), P(sos_settings), vp, P(vp)]
     lib.sos_step.argtypes = [vp, C.c_int32, P(sos_info)]
+    lib.sos_step_static.argtypes = [vp, C.c_int32, P(sos_info)]
     lib.sos_solve.argtypes = [vp, P(sos_info)]
     lib.sos_warm_start.argtypes = [vp, P(C.c_double), P(C.c_double), P(C.c_double), C.c_double, C.c_double]
     lib.sos_get_solution.argtypes = [vp, P(C.c_double), P(C.c_double), P(C.c_double)]
@@ -212,6 +213,13 @@ def setup_problem(prob, settings: Optional[sos_settings] = None, stream=None) ->
 def sos_step(w: Work, iters: int) -> dict:
     info = sos_info()
     _check(load().sos_step(w.handle, int(iters), C.byref(info)), w.handle)
+    return info.as_dict()
+
+
+def sos_step_static(w: Work, iters: int) -> dict:
+    """sos_step with the launch scratch in the library's static device array (no allocation)."""
+    info = sos_info()
+    _check(load().sos_step_static(w.handle, int(iters), C.byref(info)), w.handle)
     return info.as_dict()
 
 

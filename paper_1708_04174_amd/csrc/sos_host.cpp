@@ -541,7 +541,7 @@ RunParams single_params(sos_work *w, int mode, int iters, int min_iters, double 
 }
 
 void run_single(sos_work *w, int fp64, const RunParams &rp) {
-    if (sos_launch_reset(w->d_counter, w->stream)) throw Status(SOS_E_HIP, "reset launch failed");
+    if (sos_launch_reset(rp.counter, w->stream)) throw Status(SOS_E_HIP, "reset launch failed");
     if (sos_launch_admm(fp64, w->threads, 1, rp, w->stream)) throw Status(SOS_E_HIP, "solver launch failed");
 }
 
@@ -574,6 +574,47 @@ void read_info(sos_work *w, const double *o, sos_info *info, int iters, int poli
     info->resid_ms = o[SOS_OUT_T_RES] / khz;
     info->warm_iters = (int)o[SOS_OUT_WARM];
     info->start_ms = info->end_ms = 0.0;
+}
+
+// Layout of a single-problem launch's scratch inside the static device array: the queue
+// counter, then the affine work vector, then the eigensolver area, each 256-byte aligned.
+long long static_scratch_bytes(const sos_work *w, long long *work_off, long long *eig_off) {
+    const long long a = 256;
+    *work_off = a;
+    *eig_off = *work_off + (w->work_stride + a - 1) / a * a;
+    return *eig_off + w->eig_stride;
+}
+
+// sos_step, with the launch's scratch either the handle's own (allocated at setup) or the
+// static device array (no allocation of any kind on this path)
+void step_impl(sos_work *w, int32_t iters, sos_info *info, bool static_scratch) {
+    const int fp64 = w->st.precision == SOS_FP64;
+    RunParams rp = single_params(w, RUN_STEP, iters, 0, w->st.tol);
+    if (static_scratch) {
+        long long work_off = 0, eig_off = 0;
+        const long long need = static_scratch_bytes(w, &work_off, &eig_off);
+        if (need > SOS_STATIC_SCRATCH_BYTES)
+            throw Status(SOS_E_INVAL, "problem needs " + std::to_string(need) +
+                                          " bytes of scratch; the static scratch holds " +
+                                          std::to_string((long long)SOS_STATIC_SCRATCH_BYTES));
+        void *base = nullptr;
+        if (sos_static_scratch(&base)) throw Status(SOS_E_HIP, "address of the static device scratch not found");
+        char *b = static_cast<char *>(base);
+        rp.counter = reinterpret_cast<int *>(b);
+        rp.work = b + work_off;
+        rp.eig = b + eig_off;
+    }
+    set_active(w, fp64);
+    hip_check(hipEventRecord(w->ev0, w->stream), "event");
+    run_single(w, fp64, rp);
+    hip_check(hipEventRecord(w->ev1, w->stream), "event");
+    double o[SOS_OUT_N];
+    hip_check(hipMemcpyAsync(o, w->desc.out, sizeof(o), hipMemcpyDeviceToHost, w->stream), "copy");
+    hip_check(hipStreamSynchronize(w->stream), "sync");
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, w->ev0, w->ev1), "event");
+    w->last_ms = ms;
+    read_info(w, o, info, iters, 0);
 }
 
 template <typename F>
@@ -711,21 +752,12 @@ int sos_setup(const sos_csc *A, const double *b, const double *c, const sos_cone
 
 int sos_step(sos_work *w, int32_t iters, sos_info *info) {
     if (!w || iters < 0) return SOS_E_INVAL;
-    return guarded(w, [&] {
-        const int fp64 = w->st.precision == SOS_FP64;
-        set_active(w, fp64);
-        RunParams rp = single_params(w, RUN_STEP, iters, 0, w->st.tol);
-        hip_check(hipEventRecord(w->ev0, w->stream), "event");
-        run_single(w, fp64, rp);
-        hip_check(hipEventRecord(w->ev1, w->stream), "event");
-        double o[SOS_OUT_N];
-        hip_check(hipMemcpyAsync(o, w->desc.out, sizeof(o), hipMemcpyDeviceToHost, w->stream), "copy");
-        hip_check(hipStreamSynchronize(w->stream), "sync");
-        float ms = 0.f;
-        hip_check(hipEventElapsedTime(&ms, w->ev0, w->ev1), "event");
-        w->last_ms = ms;
-        read_info(w, o, info, iters, 0);
-    });
+    return guarded(w, [&] { step_impl(w, iters, info, false); });
+}
+
+int sos_step_static(sos_work *w, int32_t iters, sos_info *info) {
+    if (!w || iters < 0) return SOS_E_INVAL;
+    return guarded(w, [&] { step_impl(w, iters, info, true); });
 }
 
 int sos_solve(sos_work *w, sos_info *info) {

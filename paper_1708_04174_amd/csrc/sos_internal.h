@@ -18,6 +18,9 @@
 
 #define SOS_MAX_BLOCKS 8
 #define SOS_KMAX_LDS 1024   // largest A_f width whose k-vector is kept in LDS
+// bytes of the per-device static scratch used by sos_step_static (queue counter, affine work
+// vector and eigensolver area of one workgroup)
+#define SOS_STATIC_SCRATCH_BYTES (4 << 20)
 
 struct ProbDesc {
     int m, nx, nfree, k, nblk, nmax;
@@ -113,4 +116,7 @@ int sos_launch_reset_state(const ProbDesc *probs_dev, int count, int max_len, vo
 // grid: the number of workgroups whose scratch areas (work_stride, eig_stride apart) exist
 int sos_launch_warm_start(int fp64, int threads, int grid, const RunParams &rp, const float *pred, long long ld,
                           void *stream);
+// Device address of the static scratch (SOS_STATIC_SCRATCH_BYTES) on the current device,
+// looked up once per device; 0 on success, -4 if the lookup failed.
+int sos_static_scratch(void **ptr);
 int sos_launch_export(int fp64, const ProbDesc *probs, int count, float *out, long long ld, int max_len, void *stream);

@@ -17,12 +17,20 @@
 //            PSD part of w parked in v for the projection.
 // The identity u_hat_tau = omega_tau + theta follows from the rank-one formula:
 // zeta^T u_hat = zeta^T sigma - theta zeta^T h = zeta^T sigma / eta = theta.
+#include <mutex>
 #include <type_traits>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 
 #include "sos_internal.h"
+
+// Device scratch of the entry point that allocates nothing (sos_step_static): the queue
+// counter, the affine work vector and the eigensolver area of its one workgroup.  Each GPU
+// the library runs on holds its own copy until the process ends.  Host code never passes
+// this name to a kernel (on the host it is a stand-in, not a device address): it takes the
+// address sos_static_scratch looked up for the current device.
+static __device__ __align__(256) char scratch[SOS_STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -1804,6 +1812,26 @@ int sos_launch_warm_start(int fp64, int threads, int grid, const RunParams &rp_i
     }
 #undef SOS_WS
     return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int sos_static_scratch(void **ptr) {
+    // one lookup per device, made with that device current, kept for the process
+    constexpr int kMaxDev = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDev] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return -4;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return -4;
+        }
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return 0;
 }
 
 int sos_launch_export(int fp64, const ProbDesc *probs, int count, float *out, long long ld, int max_len, void *stream) {
