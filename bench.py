@@ -6,7 +6,9 @@ inputs already resident on the GPU: the learned warm start (MLP inference on the
 device, the warm-start kernel), the batched persistent solve (FP32 bulk, FP64 Schur
 solve / theta / tau-kappa / residuals, FP64 polish), and cold re-solves of whatever the
 warm start left unsolved.  A solve counts when its FP64 max(r_p, r_d, r_g) <= 1e-4 or
-it ends in an infeasibility certificate.
+it ends in an infeasibility certificate, and only where the FP64 CPU oracle reaches the
+same status (a stored table written by tests/golden/make_oracle_tables.py, which calls only
+the oracle and the input generators).
 
 Default workload: 512 held-out Lyapunov programs (n = 6, quartic V; Gram blocks 28 and
 84, m = 1134).  The warm-start model is trained beforehand (untimed) on the solver's
@@ -52,25 +54,85 @@ def iter_flops(prob) -> float:
     return sum(eig_flops(N) for N in prob.psd_dims) + 4.0 * prob.A.nnz + 2.0 * k * k + 12.0 * (prob.n + prob.m)
 
 
-def cpu_baseline(probs, budget_s: float, tol: float):
+def _oracle_job(job):
+    """One oracle solve in a worker process (1 BLAS thread): (seed, status, setup_s, solve_s)."""
+    kind, seed, tol = job
     from threadpoolctl import threadpool_limits
 
     from oracle.admm import Oracle
-    t0 = time.perf_counter()
-    done, solved, names = 0, 0, []
+    from sosgen import families as F
+    prob = F.lyapunov(seed) if kind == "lyapunov" else F.pop_batch_member(seed)
     with threadpool_limits(limits=1):
-        for p in probs:
-            r = Oracle.from_problem(p).solve(tol=tol, max_iters=2000, check_every=10)
-            done += 1
-            solved += r.status in OK_STATUS
-            names.append(f"seed{p.meta.get('seed')}")
-            if time.perf_counter() - t0 > budget_s:
+        t0 = time.perf_counter()
+        o = Oracle.from_problem(prob)
+        t1 = time.perf_counter()
+        r = o.solve(tol=tol, max_iters=2000, check_every=10)
+        t2 = time.perf_counter()
+    return seed, int(r.status), t1 - t0, t2 - t1
+
+
+def _warm_worker(_):
+    import scipy.sparse  # noqa: F401  - imports paid before the timed window
+
+    import oracle.admm  # noqa: F401
+    import sosgen.families  # noqa: F401
+    return os.getpid()
+
+
+def host_cpu():
+    """(logical CPUs, CPUs this process may run on, CPU model name) of the host."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
                 break
-    el = time.perf_counter() - t0
-    return {"value": solved / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"the first {done} problems of the workload in a seeded random order, until {budget_s:.0f} s "
-                      f"were spent: one at a time, FP64, I + A A^T factored directly, 1 BLAS thread; "
-                      f"{solved} counted in {el:.1f} s ({', '.join(names[:6])}{', ...' if len(names) > 6 else ''})"}
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return os.cpu_count() or 1, avail, model
+
+
+def cpu_baseline(kind: str, seeds, budget_s: float, tol: float, ok_status):
+    """The oracle over a process pool on the host cores (at most 16 workers, one BLAS thread
+    each), fed the workload's problems in the given order until budget_s of wall time has
+    passed.  Throughput counts solve time only (the oracle's set-up, factoring I + A A^T, is
+    reported apart), like the GPU arm, whose set-up is also reported apart."""
+    import multiprocessing as mp
+    nproc, avail, model = host_cpu()
+    workers = max(1, min(16, avail))
+    for var in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"   # inherited by the spawned workers
+    ctx = mp.get_context("spawn")   # fresh interpreters: nothing of this process's GPU state
+    pool = ctx.Pool(workers)
+    try:
+        pool.map(_warm_worker, range(workers))
+        t0 = time.perf_counter()
+        done, counted, setup_s, solve_s, t_last = 0, 0, 0.0, 0.0, 0.0
+        for seed, status, su, so in pool.imap_unordered(_oracle_job, [(kind, int(s), tol) for s in seeds]):
+            done += 1
+            counted += ok_status(seed, status)
+            setup_s += su
+            solve_s += so
+            t_last = time.perf_counter() - t0
+            if t_last > budget_s:
+                break
+    finally:
+        pool.terminate()
+        pool.join()
+    return {"value": workers * counted / solve_s if solve_s > 0 else None, "unit": "solves/s", "cores": workers,
+            "kind": "oracle",
+            "value_with_setup": workers * counted / (setup_s + solve_s) if solve_s > 0 else None,
+            "wall_value": counted / t_last if t_last > 0 else None,
+            "setup_ms_per_problem": 1e3 * setup_s / max(done, 1),
+            "nproc": nproc, "cpus_available": avail, "cpu_model": model,
+            "sample": f"{done} problems of the workload in a seeded random order, solved by a pool of {workers} "
+                      f"worker processes until {budget_s:.0f} s of wall time had passed (FP64, I + A A^T factored "
+                      f"directly, 1 BLAS thread each); {counted} counted; value = workers x counted / summed "
+                      f"solve time (set-up excluded, as in the GPU arm)"}
 
 
 COPY_PROBE_BYTES = 256 * 1024 * 1024
@@ -100,6 +162,17 @@ def measured_traffic(kernel: str, workload: str, sched):
             rec.get("kernel_source_sha256") != src or rec.get("schedule_sha256") != sched_sha:
         return None
     return float(rec["hbm_bytes_per_launch"])
+
+
+def oracle_statuses(workload: str):
+    """Stored FP64 oracle status per seed for the workload, or None if no table covers it."""
+    f = os.path.join(ROOT, "tests", "golden", "oracle_tables.json")
+    if not os.path.exists(f):
+        return None
+    tab = json.load(open(f)).get(workload)
+    if not tab:
+        return None
+    return {int(k): int(v["status"]) for k, v in tab["seeds"].items()}
 
 
 def load_schedule(name: str, override):
@@ -132,6 +205,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-batched-fp64", action="store_true")
     ap.add_argument("--dump-infos", default=None,
                     help="write the per-problem records of the last timed step (status, iterations, "
                          "queue start / finish in ms) to this JSON file")
@@ -171,14 +245,29 @@ def main():
         probs = WL.generate("pop_batch", range(512))
         train_probs = []
     log(f"[bench] generated {len(probs)} + {len(train_probs)} problems in {time.perf_counter() - t0:.1f}s")
+    seeds = test_seeds if lyap else list(range(512))
+    # a result counts where it is a solution or certificate the FP64 oracle agrees with
+    ost = oracle_statuses(args.workload)
+
+    def ok_status(seed, status):
+        return status in OK_STATUS and (ost is None or ost.get(int(seed)) == status)
+
+    def n_ok(infos, idx=None):
+        idx = range(len(infos)) if idx is None else idx
+        return int(sum(ok_status(seeds[j], inf["status"]) for j, inf in zip(idx, infos)))
     sched = load_schedule(args.workload, args.schedule)
     st = B.sos_default_settings(tol=args.tol, max_iters=2000, check_every=10,
                                 precision=B.SOS_FP32_MIXED, polish_iters=1)
     t0 = time.perf_counter()
     works = [B.setup_problem(p, st) for p in probs]
+    t_setup = time.perf_counter() - t0
     batch = B.sos_batch_setup(works, sched)
+    t_bsetup = time.perf_counter() - t0 - t_setup
     layout = B.sos_layout_size(works[0])
-    log(f"[bench] setup {time.perf_counter() - t0:.1f}s")
+    gpu_setup = {"ms_per_problem": 1e3 * t_setup / len(probs), "batch_setup_ms": 1e3 * t_bsetup,
+                 "note": "sos_setup on the host (validation, partition, S and its inverse, h) plus the upload, "
+                         "then sos_batch_setup; outside the timed step, like the oracle's set-up"}
+    log(f"[bench] setup {t_setup:.1f}s + batch {t_bsetup:.1f}s")
 
     # ---------------------------------------------------------------- warm-start model (untimed)
     model, train_info = None, None
@@ -225,7 +314,7 @@ def main():
         return infos, (time.perf_counter() - t) * 1e3
 
     cinfos, cms = cold_step()
-    cold = {"value": sum(i["status"] in OK_STATUS for i in cinfos) / (cms / 1e3), "ms": cms,
+    cold = {"value": n_ok(cinfos) / (cms / 1e3), "ms": cms,
             "iters_mean": float(np.mean([i["iters"] for i in cinfos]))}
     log(f"[bench] cold batched: {cold}")
 
@@ -250,7 +339,7 @@ def main():
     for i in range(args.steps):
         torch.cuda.synchronize()
         infos, ms, nfb = step()
-        ok = sum(inf["status"] in OK_STATUS for inf in infos)
+        ok = n_ok(infos)
         step_ms.append(ms)
         counted.append(ok)
         tb = warm_batch if model is not None else batch
@@ -268,6 +357,12 @@ def main():
     statuses = {}
     for inf in infos:
         statuses[inf["status_name"]] = statuses.get(inf["status_name"], 0) + 1
+    agreement = None
+    if ost is not None:
+        agreement = {}
+        for sd, inf in zip(seeds, infos):
+            key = f"gpu_{inf['status_name']}/oracle_{B.STATUS_NAMES.get(ost[int(sd)])}"
+            agreement[key] = agreement.get(key, 0) + 1
     iters = np.array([inf["iters"] for inf in infos])
     solved = [inf for inf in infos if inf["status"] == 1]
     worst = max(max(i["res_pri"], i["res_dual"], i["gap"]) for i in solved) if solved else None
@@ -342,29 +437,59 @@ def main():
                      "warm_iters_median": float(np.median([first[i]["iters"] for i in both])) if both else None}
         log(f"[bench] warm start gain: {warm_gain}")
 
-    plain = None
+    plain, unbatched32 = None, None
     if not args.no_plain:
+        # one problem per launch (one workgroup on one CU), cold start: every step FP64 (the
+        # plain arm), and the mixed form (FP32 bulk, FP64 islands and polish) unbatched
         ns = args.plain_sample or (32 if lyap else 4)
         idx = np.linspace(0, len(probs) - 1, ns).astype(int)
+        arms = {}
+        for name, prec in (("fp64", B.SOS_FP64), ("fp32_mixed", B.SOS_FP32_MIXED)):
+            sx = B.sos_default_settings(tol=args.tol, max_iters=2000, check_every=10, precision=prec, polish_iters=1)
+            tms, okx = 0.0, 0
+            for i in idx:
+                w = B.setup_problem(probs[i], sx)
+                inf = B.sos_solve(w)
+                tms += inf["solve_ms"]
+                okx += ok_status(seeds[i], inf["status"])
+                w.free()
+            arms[name] = {"value": okx / (tms / 1e3), "unit": "solves/s", "ms_total": tms, "counted": okx,
+                          "sample": f"{len(idx)} problems spread over the workload, sos_solve one at a time, "
+                                    f"{'every step FP64' if name == 'fp64' else 'FP32 bulk with FP64 islands'}, "
+                                    "cold start"}
+            log(f"[bench] unbatched {name}: {arms[name]['value']:.2f} solves/s")
+        plain, unbatched32 = arms["fp64"], arms["fp32_mixed"]
+
+    batched64 = None
+    if not args.no_batched_fp64:
+        # the whole workload in one persistent launch, every step FP64, cold start
         s64 = B.sos_default_settings(tol=args.tol, max_iters=2000, check_every=10, precision=B.SOS_FP64)
-        tms, ok64 = 0.0, 0
-        for i in idx:
-            w = B.setup_problem(probs[i], s64)
-            inf = B.sos_solve(w)
-            tms += inf["solve_ms"]
-            ok64 += inf["status"] in OK_STATUS
+        works64 = [B.setup_problem(p, s64) for p in probs]
+        batch64 = B.sos_batch_setup(works64, sched)
+        b64 = []
+        for rep in range(2):   # the first run captures the graph
+            B.sos_batch_reset(batch64)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            i64 = B.sos_batch_solve(batch64)
+            torch.cuda.synchronize()
+            b64.append(((time.perf_counter() - t) * 1e3, i64))
+        ms64, i64 = b64[-1]
+        batched64 = {"value": n_ok(i64) / (ms64 / 1e3), "unit": "solves/s", "ms": ms64, "counted": n_ok(i64),
+                     "iters_mean": float(np.mean([i["iters"] for i in i64])),
+                     "sample": "the whole workload in one persistent launch, every step FP64, cold start"}
+        log(f"[bench] batched FP64: {batched64['value']:.1f} solves/s ({ms64:.0f} ms)")
+        batch64.free()
+        for w in works64:
             w.free()
-        plain = {"value": ok64 / (tms / 1e3), "unit": "solves/s", "ms_total": tms,
-                 "sample": f"{len(idx)} problems spread over the workload, sos_solve one at a time, every step FP64, "
-                           "cold start"}
-        log(f"[bench] plain FP64: {plain['value']:.2f} solves/s")
 
     cpu = None
     if not args.no_cpu_baseline:
         # the workload in a seeded random order, solved until the time budget is spent
         order = np.random.default_rng(0).permutation(len(probs))
-        cpu = cpu_baseline([probs[i] for i in order], args.cpu_budget, args.tol)
-        log(f"[bench] cpu baseline: {cpu['value']:.3f} solves/s")
+        cpu = cpu_baseline("lyapunov" if lyap else "pop_batch", [seeds[i] for i in order], args.cpu_budget,
+                           args.tol, ok_status)
+        log(f"[bench] cpu baseline: {cpu['value']:.3f} solves/s on {cpu['cores']} cores ({cpu['cpu_model']})")
 
     desc = ("512 held-out Lyapunov programs (n = 6, quartic V: 203 free variables, Gram blocks 28 and 84, "
             "m = 1134; seeds 3584..4095), learned warm start + batched FP32 bulk / FP64 polish"
@@ -375,13 +500,18 @@ def main():
         "warmup": args.warmup, "ms_per_step": total_ms / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "problems": len(probs), "tol": args.tol,
-                   "statuses": statuses, "iters_mean": float(iters.mean()), "iters_median": float(np.median(iters)),
+                   "statuses": statuses, "oracle_agreement": agreement,
+                   "counted_rule": "SOLVED at FP64 residual <= tol or a certificate, and the same status as the "
+                                   "FP64 CPU oracle" + ("" if ost is not None else " (no oracle table: unchecked)"),
+                   "iters_mean": float(iters.mean()), "iters_median": float(np.median(iters)),
                    "iters_max": int(iters.max()), "fallbacks": int(np.sum(fbs)), "worst_solved_residual": worst,
                    "phase_ms": {"solve_kernel": k_ms, "polish_kernel": float(pms[-1])},
                    "schedule": json.loads(sched) if sched else None, "warm_start_model": train_info},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "setup": {"gpu": gpu_setup, "oracle_ms_per_problem": cpu["setup_ms_per_problem"] if cpu else None},
         "plain_fp64": plain,
+        "ablations": {"batched_cold_fp32": cold, "batched_fp64": batched64, "unbatched_fp32_mixed": unbatched32},
         "batched_cold_fp32": cold,
         "warm_start_gain": warm_gain,
         "speedup_vs_plain_fp64": (value / plain["value"]) if plain else None,
