@@ -137,6 +137,41 @@ def cpu_baseline(kind: str, seeds, budget_s: float, tol: float, ok_status):
 
 COPY_PROBE_BYTES = 256 * 1024 * 1024
 
+PER_ITER_CASES = {
+    # name: (generator, description)
+    "lyapunov": (lambda F: F.lyapunov(3584), "Lyapunov program, seed 3584: blocks 84 + 28, m = 1134, k = 203"),
+    "pop_n6": (lambda F: F.pop_unconstrained(6, 0), "quartic POP n = 6: block 28, m = 210"),
+    "pop_n10": (lambda F: F.pop_unconstrained(10, 0), "quartic POP n = 10: block 66, m = 1001"),
+    "pop_n14": (lambda F: F.pop_unconstrained(14, 0), "quartic POP n = 14: block 120, m = 3060"),
+    "ball_n16": (lambda F: F.pop_ball(16, 0), "ball POP n = 16: blocks 153 + 17, m = 4845, k = 154"),
+    "pop_n20": (lambda F: F.pop_unconstrained(20, 0, cross_std=0.1), "quartic POP n = 20: block 231, m = 10626"),
+}
+
+
+def per_iteration(cases, warm_iters: int, timed_iters: int):
+    """ms per iteration of sos_step on single problems (one workgroup), after warm_iters
+    iterations (warm Jacobi starts settled), in both precision forms, with the device-clock
+    split by phase and the mean Jacobi sweeps per block."""
+    from paper_1708_04174_amd import binding as B
+    from sosgen import families as F
+    out = []
+    for name in cases:
+        gen, desc = PER_ITER_CASES[name]
+        prob = gen(F)
+        for prec, pname in ((B.SOS_FP32_MIXED, "fp32"), (B.SOS_FP64, "fp64")):
+            w = B.setup_problem(prob, B.sos_default_settings(precision=prec))
+            B.sos_step(w, warm_iters)
+            inf = B.sos_step(w, timed_iters)
+            w.free()
+            rec = {"case": name, "description": desc, "precision": pname, "iters": timed_iters,
+                   "after": warm_iters, "ms_per_iter": inf["solve_ms"] / timed_iters,
+                   "affine_ms_per_iter": inf["affine_ms"] / timed_iters,
+                   "projection_ms_per_iter": inf["eig_ms"] / timed_iters, "sweeps": inf["eig_sweeps"]}
+            log(f"[per-iter] {name} {pname}: {rec['ms_per_iter']:.3f} ms/iter (affine {rec['affine_ms_per_iter']:.3f}, "
+                f"projection {rec['projection_ms_per_iter']:.3f}, {rec['sweeps']:.1f} sweeps)")
+            out.append(rec)
+    return out
+
 
 def _sha256(path: str) -> str:
     import hashlib
@@ -209,6 +244,9 @@ def main():
     ap.add_argument("--dump-infos", default=None,
                     help="write the per-problem records of the last timed step (status, iterations, "
                          "queue start / finish in ms) to this JSON file")
+    ap.add_argument("--per-iter", nargs="*", default=None, metavar="CASE",
+                    help="only time sos_step per iteration on single problems (cases: "
+                         + ", ".join(PER_ITER_CASES) + "; none given: all) and print them as one JSON line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 256 MiB device buffer three times (the known-size kernel that "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -229,6 +267,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": COPY_PROBE_BYTES, "copies": 3}), flush=True)
+        return
+    if args.per_iter is not None:
+        cases = args.per_iter or list(PER_ITER_CASES)
+        print(json.dumps({"per_iteration": per_iteration(cases, 100, 50)}), flush=True)
         return
     from paper_1708_04174_amd import binding as B
     from paper_1708_04174_amd import warmstart as W

@@ -561,6 +561,143 @@ __device__ __forceinline__ int os_rotate_pair(GP G, int ldg, VP V, int ldv, int 
     return ga * ga > tol * (al * be) ? 2 : 1;
 }
 
+// ----------------------------------------------------------------------------- MFMA tiles
+// The projection's two dense products run on the matrix cores, one 16 x 16 output tile per
+// wavefront and 16 x 16 x 4 MFMA steps (FP32 MFMA with FP32 accumulation in the FP32 phase,
+// FP64 MFMA in the FP64 phase).  Operand layout of one step D += A B (A 16 x 4, B 4 x 16):
+// lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; its four results r = 0..3 are
+// D[row(l / 16, r)][l % 16], with row = 4 (l / 16) + r for FP32 and l / 16 + 4 r for FP64
+// (layouts measured on gfx950).  Entries outside the N x N matrices are zero.
+template <typename T> struct Mma;
+template <> struct Mma<float> {
+    typedef float acc __attribute__((ext_vector_type(4)));
+    __device__ static __forceinline__ acc step(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int lg, int r) { return 4 * lg + r; }
+};
+template <> struct Mma<double> {
+    typedef double acc __attribute__((ext_vector_type(4)));
+    __device__ static __forceinline__ acc step(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int lg, int r) { return lg + 4 * r; }
+};
+
+// Output tiles a wavefront may hold in registers while W, stored where G goes, is still read.
+constexpr int kMfmaHold = 8;
+
+// G = W V for column-major N x N matrices, W symmetric.  In a chunk of 16 values of the
+// summation index, lane group g = l / 16 takes k = k0 + 4 g + t in step t = 0..3, so each lane
+// reads four consecutive entries of a column of V (and, W being symmetric, of a column of W)
+// per chunk.  W in global memory (wglobal) is read by rows instead, W[k][i] for consecutive i
+// across lanes, which keeps those reads coalesced.  hold: W occupies G's storage; every tile
+// stays in registers until all wavefronts have finished reading W (needs at most kMfmaHold
+// tiles per wavefront).  The caller ends with a barrier before G is read.
+template <typename T, int NT, typename WP, typename VP, typename GP>
+__device__ __forceinline__ void mfma_wv(WP W, int ldw, bool wglobal, VP V, int ldv, GP G, int ldg, int N,
+                                        bool hold) {
+    typedef typename Mma<T>::acc AC;
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int nt = (N + 15) >> 4, ntt = nt * nt;
+    for (int base = 0; base < ntt; base += NW * kMfmaHold) {
+        AC acc[kMfmaHold];
+#pragma unroll
+        for (int q = 0; q < kMfmaHold; ++q) {
+            acc[q] = (AC)(T)0;
+            const int tile = base + q * NW + wid;   // wavefront-uniform
+            if (tile >= ntt) continue;
+            const int i0 = (tile % nt) * 16, j0 = (tile / nt) * 16;
+            const int i = i0 + li, j = j0 + li;   // this lane's row of A, column of B
+            const bool iok = i < N, jok = j < N;
+            for (int k0 = 0; k0 < N; k0 += 16) {
+                const int kb = k0 + 4 * lg;
+                T a[4], b[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const bool kok = kb + t < N;
+                    a[t] = (iok && kok) ? (wglobal ? W[(long long)(kb + t) * ldw + i] : W[(long long)i * ldw + kb + t])
+                                        : (T)0;
+                    b[t] = (jok && kok) ? V[(long long)j * ldv + kb + t] : (T)0;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[q] = Mma<T>::step(a[t], b[t], acc[q]);
+            }
+        }
+        if (hold) __syncthreads();   // every read of W done before G, its storage, is written
+#pragma unroll
+        for (int q = 0; q < kMfmaHold; ++q) {
+            const int tile = base + q * NW + wid;
+            if (tile >= ntt) continue;
+            const int i0 = (tile % nt) * 16, j = (tile / nt) * 16 + li;
+            if (j >= N) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + Mma<T>::row(lg, r);
+                if (i < N) G[(long long)j * ldg + i] = acc[q][r];
+            }
+        }
+    }
+}
+
+// Lower triangle of (W + V Sigma V^T) / 2 into us, and v = u - w into vs (both packed lower
+// triangles by columns; vs holds w on entry).  Tiles on and below the diagonal, one per
+// wavefront at a time; step t covers V's columns k0 + l / 16.
+template <typename T, int NT, typename VP, typename SP>
+__device__ __forceinline__ void mfma_rebuild(VP V, int ldv, SP sig, int N, T *__restrict__ vs, T *__restrict__ us) {
+    typedef typename Mma<T>::acc AC;
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int nt = (N + 15) >> 4, ntri = nt * (nt + 1) / 2;
+    for (int tile = wid; tile < ntri; tile += NW) {
+        int ta = 0, rem = tile;
+        while (rem > ta) {
+            rem -= ta + 1;
+            ++ta;
+        }
+        const int i0 = ta * 16, j0 = rem * 16;   // tile row ta >= tile column rem
+        const int i = i0 + li, j = j0 + li;
+        const bool iok = i < N, jok = j < N, diag = ta == rem;
+        AC acc = (AC)(T)0;
+        int k0 = 0;
+        for (; k0 + 16 <= N; k0 += 16) {
+            T a[4], b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = k0 + 4 * t + lg;
+                const T vi = iok ? V[(long long)k * ldv + i] : (T)0;
+                b[t] = diag ? vi : (jok ? V[(long long)k * ldv + j] : (T)0);
+                a[t] = vi * sig[k];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc = Mma<T>::step(a[t], b[t], acc);
+        }
+        for (; k0 < N; k0 += 4) {
+            const int k = k0 + lg;
+            const bool kok = k < N;
+            const T vi = (iok && kok) ? V[(long long)k * ldv + i] : (T)0;
+            const T b = diag ? vi : ((jok && kok) ? V[(long long)k * ldv + j] : (T)0);
+            const T a = kok ? vi * sig[k] : (T)0;
+            acc = Mma<T>::step(a, b, acc);
+        }
+        if (!jok) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ii = i0 + Mma<T>::row(lg, r);
+            if (ii < N && ii >= j) {
+                const int s = svec_idx(ii, j, N);
+                const T w = vs[s];
+                const T x = (T)0.5 * (w + acc[r]);
+                us[s] = x;
+                vs[s] = x - w;
+            }
+        }
+    }
+}
+
 // Projects one block: the lower triangle of W is read from vs, the lower triangle of
 // P_{S+}(W) is written to us and v = u - w back to vs.
 // P_{S+}(W) = (W + |W|) / 2 with |W| = V Sigma V^T: one-sided (Hestenes) Jacobi makes the
@@ -589,11 +726,11 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
         return;
     }
     // G = W (cold, V = I) or G = W V_prev (warm); W is symmetric, so column j of W = row j.
-    // Warm, with at most one 4 x 4 tile of G per thread, W is staged where G goes and each
-    // thread keeps its tile of W V in registers until every read of W is done; otherwise W
-    // is staged in the global scratch Tm.
-    const int nt = (N + 3) >> 2;
-    const bool wreg = warm && nt * nt <= NT;
+    // Warm, with at most kMfmaHold 16 x 16 tiles of G per wavefront, W is staged where G goes
+    // and each wavefront keeps its tiles of W V in registers until every read of W is done;
+    // otherwise W is staged in the global scratch Tm.
+    const int nt16 = (N + 15) >> 4;
+    const bool wreg = warm && nt16 * nt16 <= NW * kMfmaHold;
     // four entries per thread and pass, their global reads issued together
     double fro2 = 0.0, dummy = 0.0;
     for (int base = 0; base < N * N; base += 4 * NT) {
@@ -624,68 +761,11 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
         }
     }
     __syncthreads();
-    if (wreg) {
-        // G[:, j] = sum_k W[:, k] V[k, j], one tile per thread, W read from G's storage.
-        // Consecutive threads take consecutive row tiles of one column tile: a wavefront then
-        // reads a few columns of V (broadcast) and consecutive rows of W, where column tiles
-        // at stride ld would put its V reads in a couple of banks
-        const bool act = tid < nt * nt;
-        const int j0 = (tid / nt) * 4, i0 = (tid - (tid / nt) * nt) * 4;
-        T acc[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
-        if (act) {
-#pragma unroll 4
-            for (int kk = 0; kk < N; ++kk) {
-                T wa[4], vb[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) wa[a] = (i0 + a < N) ? G[kk * ld + i0 + a] : (T)0;   // W[i][k]
-#pragma unroll
-                for (int b = 0; b < 4; ++b) vb[b] = (j0 + b < N) ? V[(j0 + b) * ld + kk] : (T)0;   // V[k][j]
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[a][b] += wa[a] * vb[b];
-            }
-        }
-        __syncthreads();   // every read of W done before G overwrites it
-        if (act) {
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    if (i0 + a < N && j0 + b < N) G[(j0 + b) * ld + i0 + a] = acc[a][b];
-        }
-        __syncthreads();
-    } else if (warm) {
-        // G[:, j] = sum_k W[:, k] V[k, j]  (column-major: G^T = V^T W^T, computed as (V^T W)^T)
-        for (int t = tid; t < nt * nt; t += NT) {
-            const int j0 = (t / nt) * 4, i0 = (t - (t / nt) * nt) * 4;   // row tiles fastest (bank spread)
-            T acc[4][4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
-#pragma unroll 4
-            for (int kk = 0; kk < N; ++kk) {
-                T wa[4], vb[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) wa[a] = (i0 + a < N) ? Tm[kk * N + i0 + a] : (T)0;   // W[i][k]
-#pragma unroll
-                for (int b = 0; b < 4; ++b) vb[b] = (j0 + b < N) ? V[(j0 + b) * ld + kk] : (T)0;   // V[k][j]
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[a][b] += wa[a] * vb[b];
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    if (i0 + a < N && j0 + b < N) G[(j0 + b) * ld + i0 + a] = acc[a][b];
-        }
+    if (warm) {
+        // G = W V_prev on the matrix cores; W read from G's storage (held tiles) or from Tm
+        constexpr bool g_lds = std::is_same<GP, typename Lds<T>::type *>::value;
+        if (wreg) mfma_wv<T, NT>(G, ld, !g_lds, V, ld, G, ld, N, true);
+        else mfma_wv<T, NT>(Tm, N, true, V, ld, G, ld, N, false);
         __syncthreads();
     }
     block_sum2<NT>(fro2, dummy, sc.s_red);
@@ -754,48 +834,8 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
         if (lane == 0) s_sig[j] = sqrt(s);
     }
     __syncthreads();
-    // u = lower((W + V Sigma V^T) / 2), v = u - w, by 4 x 4 tiles on and below the diagonal
-    const int ntri = nt * (nt + 1) / 2;
-    for (int t = tid; t < ntri; t += NT) {
-        int ta = 0, rem = t;
-        while (rem > ta) {
-            rem -= ta + 1;
-            ++ta;
-        }
-        const int a0 = ta * 4, b0 = rem * 4;   // tile row ta >= tile column rem
-        T acc[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
-        // four columns of V per step: their LDS reads are in flight together
-#pragma unroll 4
-        for (int j = 0; j < N; ++j) {
-            const T sg = s_sig[j];
-            T va[4], vb[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) va[a] = (a0 + a < N) ? V[j * ld + a0 + a] * sg : (T)0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) vb[b] = (b0 + b < N) ? V[j * ld + b0 + b] : (T)0;
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] += va[a] * vb[b];
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int i = a0 + a, j = b0 + b;
-                if (i < N && j <= i) {
-                    const int s = svec_idx(i, j, N);
-                    const T w = vs[s];
-                    const T x = (T)0.5 * (w + acc[a][b]);
-                    us[s] = x;
-                    vs[s] = x - w;
-                }
-            }
-    }
+    // u = lower((W + V Sigma V^T) / 2), v = u - w, on the matrix cores
+    mfma_rebuild<T, NT>(V, ld, s_sig, N, vs, us);
     if (Vs)
         for (int idx = tid; idx < N * N; idx += NT) {
             const int j = idx / N, i = idx - (idx / N) * N;
@@ -928,33 +968,8 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
     }
     block_sum2<NT>(fro2, dummy, sc.s_red);   // its barriers also publish G, V, Tm
     if (warm) {
-        // G = W V_prev, 4 x 4 tiles over the workgroup
-        const int nt = (N + 3) >> 2;
-        for (int t = tid; t < nt * nt; t += NT) {
-            const int j0 = (t / nt) * 4, i0 = (t - (t / nt) * nt) * 4;   // row tiles fastest (bank spread)
-            T acc[4][4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
-#pragma unroll 4
-            for (int kk = 0; kk < N; ++kk) {
-                T wa[4], vb[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) wa[a] = (i0 + a < N) ? Tm[kk * N + i0 + a] : (T)0;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) vb[b] = (j0 + b < N) ? V[(j0 + b) * ld + kk] : (T)0;
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[a][b] += wa[a] * vb[b];
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    if (i0 + a < N && j0 + b < N) G[(j0 + b) * ld + i0 + a] = acc[a][b];
-        }
+        // G = W V_prev on the matrix cores (W in Tm; rows N.. of G stay zero)
+        mfma_wv<T, NT>(Tm, N, true, V, ld, G, ld, N, false);
         __syncthreads();
     }
     const T tol = jacobi_tol<T>(sc.jtol);
@@ -1147,48 +1162,8 @@ __device__ __noinline__ void project_block_rows(T *__restrict__ vs, T *__restric
         sig[j] = sqrt(hsum<T>(s));
     }
     __syncthreads();
-    // u = lower((W + V Sigma V^T) / 2), v = u - w, 4 x 4 tiles on and below the diagonal
-    const int nt = (N + 3) >> 2;
-    const int ntri = nt * (nt + 1) / 2;
-    for (int t = tid; t < ntri; t += NT) {
-        int ta = 0, rem = t;
-        while (rem > ta) {
-            rem -= ta + 1;
-            ++ta;
-        }
-        const int a0 = ta * 4, b0 = rem * 4;
-        T acc[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
-#pragma unroll 4
-        for (int j = 0; j < N; ++j) {
-            const T sg = sig[j];
-            T va[4], vb[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) va[a] = (a0 + a < N) ? V[j * ld + a0 + a] * sg : (T)0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) vb[b] = (b0 + b < N) ? V[j * ld + b0 + b] : (T)0;
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] += va[a] * vb[b];
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int i = a0 + a, j = b0 + b;
-                if (i < N && j <= i) {
-                    const int s = svec_idx(i, j, N);
-                    const T x0 = vs[s];
-                    const T x = (T)0.5 * (x0 + acc[a][b]);
-                    us[s] = x;
-                    vs[s] = x - x0;
-                }
-            }
-    }
+    // u = lower((W + V Sigma V^T) / 2), v = u - w, on the matrix cores
+    mfma_rebuild<T, NT>(V, ld, sig, N, vs, us);
     if (Vs)
         for (int idx = tid; idx < N * N; idx += NT) {
             const int j = idx / N, i = idx - (idx / N) * N;
