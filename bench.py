@@ -230,6 +230,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="lyapunov_512", choices=["lyapunov_512", "pop_batch_512"])
     ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--alpha", type=float, default=1.0, help="over-relaxation of every solve (1: the paper's steps)")
+    ap.add_argument("--scale-iters", type=int, default=0,
+                    help="passes of the block-scalar equilibration of every problem (0: none)")
     ap.add_argument("--schedule", default=None)
     ap.add_argument("--train-count", type=int, default=3584)
     ap.add_argument("--epochs", type=int, default=40)
@@ -298,7 +301,7 @@ def main():
         idx = range(len(infos)) if idx is None else idx
         return int(sum(ok_status(seeds[j], inf["status"]) for j, inf in zip(idx, infos)))
     sched = load_schedule(args.workload, args.schedule)
-    st = B.sos_default_settings(tol=args.tol, max_iters=2000, check_every=10,
+    st = B.sos_default_settings(tol=args.tol, max_iters=2000, check_every=10, alpha=args.alpha, scale_iters=args.scale_iters,
                                 precision=B.SOS_FP32_MIXED, polish_iters=1)
     t0 = time.perf_counter()
     works = [B.setup_problem(p, st) for p in probs]
@@ -341,7 +344,7 @@ def main():
                       "data_s": t1 - t0, "fit_s": time.perf_counter() - t1}
         log(f"[bench] model: {train_info}")
         Xte = torch.from_numpy(WL.lyapunov_features(test_seeds)).cuda()
-        st_warm = B.sos_default_settings(tol=args.tol, max_iters=2000, check_every=10,
+        st_warm = B.sos_default_settings(tol=args.tol, max_iters=2000, check_every=10, alpha=args.alpha, scale_iters=args.scale_iters,
                                          precision=B.SOS_FP32_MIXED, polish_iters=1, warm_budget=args.warm_budget)
         warm_works = [B.setup_problem(p, st_warm) for p in probs]
         warm_batch = B.sos_batch_setup(warm_works, sched)
@@ -487,7 +490,7 @@ def main():
         idx = np.linspace(0, len(probs) - 1, ns).astype(int)
         arms = {}
         for name, prec in (("fp64", B.SOS_FP64), ("fp32_mixed", B.SOS_FP32_MIXED)):
-            sx = B.sos_default_settings(tol=args.tol, max_iters=2000, check_every=10, precision=prec, polish_iters=1)
+            sx = B.sos_default_settings(tol=args.tol, max_iters=2000, check_every=10, alpha=args.alpha, scale_iters=args.scale_iters, precision=prec, polish_iters=1)
             tms, okx = 0.0, 0
             for i in idx:
                 w = B.setup_problem(probs[i], sx)
@@ -505,7 +508,7 @@ def main():
     batched64 = None
     if not args.no_batched_fp64:
         # the whole workload in one persistent launch, every step FP64, cold start
-        s64 = B.sos_default_settings(tol=args.tol, max_iters=2000, check_every=10, precision=B.SOS_FP64)
+        s64 = B.sos_default_settings(tol=args.tol, max_iters=2000, check_every=10, alpha=args.alpha, scale_iters=args.scale_iters, precision=B.SOS_FP64)
         works64 = [B.setup_problem(p, s64) for p in probs]
         batch64 = B.sos_batch_setup(works64, sched)
         b64 = []
@@ -542,6 +545,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": total_ms / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "problems": len(probs), "tol": args.tol,
+                   "alpha": args.alpha, "scale_iters": args.scale_iters,
                    "statuses": statuses, "oracle_agreement": agreement,
                    "counted_rule": "SOLVED at FP64 residual <= tol or a certificate, and the same status as the "
                                    "FP64 CPU oracle" + ("" if ost is not None else " (no oracle table: unchecked)"),

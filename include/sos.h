@@ -105,6 +105,16 @@ typedef struct {
                                 check is restarted in the same launch from the cold start with the
                                 full max_iters budget (cold ADMM as the fallback); the abandoned
                                 iterations are reported in sos_info.warm_iters */
+    int32_t scale_iters;     /* 0: no scaling (the paper's method).  > 0: that many passes of a
+                                block-scalar equilibration before the solve: rows scaled by D,
+                                columns by E with one factor per PSD block and per free variable
+                                (Ruiz's passes on 2-norms, D balanced to geometric mean 1, factors
+                                in [1e-4, 1e4]), which keeps A_s A_s^T diagonal (Proposition 1) and
+                                the cone.  The iteration runs on D A E, D b, E c; residuals,
+                                certificates, sos_get_solution / get_iterate / set_iterate /
+                                warm_start use the original units.  The batch learned-warm-start
+                                layout (sos_batch_warm_start / export_solutions) is the scaled
+                                problem's.  0..1000, else SOS_E_INVAL. */
 } sos_settings;
 
 typedef struct {
@@ -126,7 +136,7 @@ typedef struct {
                                    wall clock); 0 for single solves */
 } sos_info;
 
-/* Fills *s with tol 1e-4, max_iters 2000, check_every 10, alpha 1, SOS_FP64,
+/* Fills *s with tol 1e-4, max_iters 2000, check_every 10, alpha 1, SOS_FP64, scale_iters 0,
    polish_iters 1, SOS_PART_PAPER, block_threads 0.  Returns SOS_E_INVAL if s is NULL. */
 int sos_default_settings(sos_settings *s);
 

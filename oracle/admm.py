@@ -70,6 +70,45 @@ def validate(A, b, c, n_free: int, psd_dims: List[int]) -> None:
         off += N * N
 
 
+def block_scalar_equilibration(A, n_free: int, psd_dims: List[int], iters: int):
+    """Row scaling D (m) and column scaling E (n) with E constant on every PSD block.
+
+    Ruiz's alternating equilibration (rows and columns divided by the square roots of their
+    norms, repeated), restricted so that the scaled matrix D A E keeps partial orthogonality:
+    a diagonal D keeps A_s A_s^T diagonal (D A_s A_s^T D), and one factor e per PSD block keeps
+    the block's columns, hence the cone, intact (A_s e^2 A_s^T).  Norms are 2-norms over the
+    full-vec columns; a PSD block's factor uses the root mean square of its N^2 column norms;
+    each free variable is its own group.  D A E does not fix how the scaling splits between D
+    and E ((s D, E / s) gives the same matrix but shifts the weight between primal and dual
+    residuals), and with m != n the passes drift in s, so after every pass D is divided by its
+    geometric mean and E multiplied by it: the row scaling stays neutral on average.  Then the
+    factors are clamped to [1e-4, 1e4].  Rows and column groups cannot all reach norm 1 unless
+    m equals n (both conditions fix the Frobenius norm of D A E); the passes drive every row
+    to one common norm and every group to another."""
+    A = sp.csc_matrix(A, dtype=np.float64)
+    m, n = A.shape
+    D = np.ones(m)
+    E = np.ones(n)
+    groups = [(j, j + 1) for j in range(n_free)]
+    off = n_free
+    for N in psd_dims:
+        groups.append((off, off + N * N))
+        off += N * N
+    A2 = A.multiply(A).tocsc()     # squared entries
+    for _ in range(iters):
+        r = np.sqrt(np.asarray((A2 @ (E * E))).ravel()) * D        # |row_i of D A E|
+        D = D / np.sqrt(np.where(r > 0, r, 1.0))
+        cn2 = np.asarray(A2.T @ (D * D)).ravel() * E * E            # |col_j of D A E|^2
+        for a, b in groups:
+            val = np.sqrt(cn2[a:b].mean())
+            if val > 0:
+                E[a:b] = E[a:b] / np.sqrt(val)
+        g = np.exp(np.mean(np.log(D)))
+        D = np.clip(D / g, 1e-4, 1e4)
+        E = np.clip(E * g, 1e-4, 1e4)
+    return D, E
+
+
 def proj_psd(W: np.ndarray) -> np.ndarray:
     """Euclidean projection of a symmetric matrix onto S_+: V max(lambda, 0) V^T."""
     S = 0.5 * (W + W.T)
@@ -104,11 +143,22 @@ class OracleResult:
 class Oracle:
     """Plain FP64 HSDE-ADMM for min c^T xi, A xi = b, xi in R^{n_free} x S^{N_1}_+ x ... (full vec)."""
 
-    def __init__(self, A, b, c, n_free: int, psd_dims: List[int], dense_limit: int = 8000):
+    def __init__(self, A, b, c, n_free: int, psd_dims: List[int], dense_limit: int = 8000, scale_iters: int = 0):
+        """scale_iters > 0: iterate on the equilibrated problem D A E, D b, E c
+        (block_scalar_equilibration); iterates, residuals and certificates are reported in the
+        original units, x = E x^, y = D y^, z = z^ / E."""
         A = sp.csc_matrix(A, dtype=np.float64)
         b = np.asarray(b, dtype=np.float64)
         c = np.asarray(c, dtype=np.float64)
         validate(A, b, c, n_free, list(psd_dims))
+        self.A0, self.A0t = A, sp.csr_matrix(A.T)   # original data: residuals are taken in its units
+        self.b0, self.c0 = b, c
+        if scale_iters > 0:
+            self.D, self.E = block_scalar_equilibration(A, n_free, list(psd_dims), scale_iters)
+            A = sp.csc_matrix(sp.diags(self.D) @ A @ sp.diags(self.E))
+            b, c = self.D * b, self.E * c
+        else:
+            self.D, self.E = np.ones(A.shape[0]), np.ones(A.shape[1])
         self.A, self.At = A, sp.csr_matrix(A.T)
         self.b, self.c = b, c
         self.m, self.n = A.shape
@@ -209,20 +259,42 @@ class Oracle:
         return u, v
 
     # ------------------------------------------------------------ termination
-    def residuals(self, u: np.ndarray, v: np.ndarray) -> dict:
+    def unscale(self, u: np.ndarray, v: np.ndarray):
+        """Iterate of the equilibrated problem -> the same iterate in the original units."""
         n, m = self.n, self.m
+        uo, vo = u.copy(), v.copy()
+        uo[:n] *= self.E
+        uo[n:n + m] *= self.D
+        vo[:n] /= self.E
+        return uo, vo
+
+    def rescale(self, u: np.ndarray, v: np.ndarray):
+        """Inverse of unscale."""
+        n, m = self.n, self.m
+        ui, vi = u.copy(), v.copy()
+        ui[:n] /= self.E
+        ui[n:n + m] /= self.D
+        vi[:n] *= self.E
+        return ui, vi
+
+    def residuals(self, u: np.ndarray, v: np.ndarray) -> dict:
+        """Residuals and certificate tests in the original units (for an equilibrated problem,
+        of the unscaled iterate: A x - b tau = D^-1 (A^ x^ - b^ tau), and so on)."""
+        n, m = self.n, self.m
+        u, v = self.unscale(u, v)
         xi, y, tau = u[:n], u[n:n + m], u[n + m]
         z, kappa = v[:n], v[n + m]
-        nb = np.linalg.norm(self.b)
-        nc = np.linalg.norm(self.c)
-        Ax = self.A @ xi
-        Aty = self.At @ y
-        cx = self.c @ xi
-        by = self.b @ y
+        b0, c0 = self.b0, self.c0
+        nb = np.linalg.norm(b0)
+        nc = np.linalg.norm(c0)
+        Ax = self.A0 @ xi
+        Aty = self.A0t @ y
+        cx = c0 @ xi
+        by = b0 @ y
         out = {"tau": tau, "kappa": kappa, "cx": cx, "by": by}
         if tau > 0.0:
-            out["res_pri"] = np.linalg.norm(Ax - self.b * tau) / tau / (1.0 + nb)
-            out["res_dual"] = np.linalg.norm(Aty + z - self.c * tau) / tau / (1.0 + nc)
+            out["res_pri"] = np.linalg.norm(Ax - b0 * tau) / tau / (1.0 + nb)
+            out["res_dual"] = np.linalg.norm(Aty + z - c0 * tau) / tau / (1.0 + nc)
             out["gap"] = abs(cx - by) / tau / (1.0 + abs(cx) / tau + abs(by) / tau)
             out["pobj"] = cx / tau
             out["dobj"] = by / tau
@@ -260,6 +332,7 @@ class Oracle:
         if r is None:
             r = self.residuals(u, v)
         n, m = self.n, self.m
+        u, v = self.unscale(u, v)
         tau = u[n + m]
         scale = 1.0 / tau if tau > 0 else 1.0
         res = OracleResult(status=status, iters=it, pobj=r["pobj"], dobj=r["dobj"], res_pri=r["res_pri"],

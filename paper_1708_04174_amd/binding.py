@@ -50,7 +50,7 @@ class sos_settings(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int32), ("check_every", C.c_int32),
                 ("alpha", C.c_double), ("precision", C.c_int32), ("polish_iters", C.c_int32),
                 ("partition", C.c_int32), ("block_threads", C.c_int32), ("eig_form", C.c_int32),
-                ("warm_budget", C.c_int32)]
+                ("warm_budget", C.c_int32), ("scale_iters", C.c_int32)]
 
 
 class sos_info(C.Structure):

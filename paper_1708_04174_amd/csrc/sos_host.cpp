@@ -110,6 +110,9 @@ struct sos_work {
     int eig_ld = 0;
     int threads = 256;
     bool active64 = true;     // which copy of (u, v) holds the current iterate
+    // equilibration: the iteration runs on D A E; x = E x^, y = D y^, z = z^ / E
+    std::vector<double> Drow; // m
+    std::vector<double> Ecol; // nx (internal columns)
     double setup_ms = 0.0, last_ms = 0.0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
@@ -154,6 +157,7 @@ void default_settings(sos_settings *s) {
     s->block_threads = 0;
     s->eig_form = 0;
     s->warm_budget = 0;
+    s->scale_iters = 0;
 }
 
 void check_settings(const sos_settings &s) {
@@ -166,6 +170,7 @@ void check_settings(const sos_settings &s) {
     if (s.precision == SOS_FP32_MIXED && s.polish_iters < 1) throw Status(SOS_E_INVAL, "polish_iters >= 1 required");
     if (s.warm_budget < 0) throw Status(SOS_E_INVAL, "warm_budget must be >= 0");
     if (s.eig_form < 0 || s.eig_form > 2) throw Status(SOS_E_INVAL, "eig_form must be 0, 1 or 2");
+    if (s.scale_iters < 0 || s.scale_iters > 1000) throw Status(SOS_E_INVAL, "scale_iters must be in 0..1000");
 }
 
 // Dense Cholesky of the k x k SPD matrix S (row-major), lower factor in place.
@@ -181,6 +186,54 @@ void cholesky(std::vector<double> &S, int k) {
             for (int p = 0; p < j; ++p) s -= S[(size_t)i * k + p] * S[(size_t)j * k + p];
             S[(size_t)i * k + j] = s / ljj;
         }
+    }
+}
+
+// Block-scalar equilibration of the full-vec A: row factors D (m) and column factors E (n),
+// E constant on every PSD block and per free variable.  Each pass divides every row by the
+// square root of its 2-norm, then every column group by the square root of the root mean
+// square of its columns' 2-norms, then rebalances D to geometric mean 1 (E takes the inverse
+// factor; D A E is unchanged) and clamps both to [1e-4, 1e4].  A diagonal D keeps A_s A_s^T
+// diagonal and one factor per block keeps the cone (Proposition 1).
+void equilibrate(const sos_csc *A, const sos_cone *K, int passes, std::vector<double> &D, std::vector<double> &E) {
+    const int m = A->m, n = A->n;
+    std::vector<double> r2(m), c2(n);
+    std::vector<int> gstart, gend;
+    for (int j = 0; j < K->n_free; ++j) {
+        gstart.push_back(j);
+        gend.push_back(j + 1);
+    }
+    int off = K->n_free;
+    for (int bk = 0; bk < K->n_psd; ++bk) {
+        gstart.push_back(off);
+        off += K->N[bk] * K->N[bk];
+        gend.push_back(off);
+    }
+    for (int pass = 0; pass < passes; ++pass) {
+        std::fill(r2.begin(), r2.end(), 0.0);
+        for (int j = 0; j < n; ++j)
+            for (long long e = A->colptr[j]; e < A->colptr[j + 1]; ++e) r2[A->rowind[e]] += A->val[e] * A->val[e] * E[j] * E[j];
+        for (int i = 0; i < m; ++i) {
+            const double r = std::sqrt(r2[i]) * D[i];
+            if (r > 0.0) D[i] /= std::sqrt(r);
+        }
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (long long e = A->colptr[j]; e < A->colptr[j + 1]; ++e) s += A->val[e] * A->val[e] * D[A->rowind[e]] * D[A->rowind[e]];
+            c2[j] = s * E[j] * E[j];
+        }
+        for (size_t g = 0; g < gstart.size(); ++g) {
+            double s = 0.0;
+            for (int j = gstart[g]; j < gend[g]; ++j) s += c2[j];
+            const double val = std::sqrt(s / (gend[g] - gstart[g]));
+            if (val > 0.0)
+                for (int j = gstart[g]; j < gend[g]; ++j) E[j] /= std::sqrt(val);
+        }
+        double lg = 0.0;
+        for (int i = 0; i < m; ++i) lg += std::log(D[i]);
+        const double gm = m > 0 ? std::exp(lg / m) : 1.0;
+        for (int i = 0; i < m; ++i) D[i] = std::min(1e4, std::max(1e-4, D[i] / gm));
+        for (int j = 0; j < n; ++j) E[j] = std::min(1e4, std::max(1e-4, E[j] * gm));
     }
 }
 
@@ -239,6 +292,32 @@ void build(sos_work *w, const sos_csc *A, const double *b, const double *c, cons
     const int nx = soff;
     w->nx = nx;
 
+    // Optional block-scalar equilibration (Ruiz's passes with one column factor per PSD block,
+    // so that partial orthogonality and the cone survive): the iteration runs on D A E, D b, E c
+    std::vector<double> aval, bsc, csc_;
+    std::vector<double> Dfull(m, 1.0), Efull(n, 1.0);
+    sos_csc Ascaled;
+    double nb0 = 0.0, nc0 = 0.0;   // norms of the original b and c (residuals are in its units)
+    for (int i = 0; i < m; ++i) nb0 += b[i] * b[i];
+    for (int j = 0; j < n; ++j) nc0 += c[j] * c[j];
+    if (w->st.scale_iters > 0) {
+        equilibrate(A, K, w->st.scale_iters, Dfull, Efull);
+        const long long nnz = A->colptr[n];
+        aval.resize(nnz);
+        for (int j = 0; j < n; ++j)
+            for (long long e = A->colptr[j]; e < A->colptr[j + 1]; ++e) aval[e] = A->val[e] * Dfull[A->rowind[e]] * Efull[j];
+        bsc.resize(m);
+        csc_.resize(n);
+        for (int i = 0; i < m; ++i) bsc[i] = b[i] * Dfull[i];
+        for (int j = 0; j < n; ++j) csc_[j] = c[j] * Efull[j];
+        Ascaled = *A;
+        Ascaled.val = aval.data();
+        A = &Ascaled;
+        b = bsc.data();
+        c = csc_.data();
+    }
+    w->Drow = Dfull;
+
     // fold to the lower triangle: column e -> source column (i,j), i >= j; an off-diagonal
     // entry stands for both (i,j) and (j,i) of the full vec, hence weight 2
     std::vector<int> src_col(nx);
@@ -253,6 +332,8 @@ void build(sos_work *w, const sos_csc *A, const double *b, const double *c, cons
                 wgt[e] = (i == j) ? 1.0 : 2.0;
             }
     }
+    w->Ecol.assign(nx, 1.0);
+    for (int e = 0; e < nx; ++e) w->Ecol[e] = Efull[src_col[e]];
     std::vector<int> cnt(nx);
     std::vector<double> cs(nx), cw(nx);
     for (int e = 0; e < nx; ++e) {
@@ -474,8 +555,16 @@ void build(sos_work *w, const sos_csc *A, const double *b, const double *c, cons
     P.cw32 = up_f(cw);
     P.wgt64 = up_d(wgt);
     P.eta = eta;
-    P.nb = std::sqrt(nb);
-    P.nc = std::sqrt(nc);
+    P.nb = w->st.scale_iters > 0 ? std::sqrt(nb0) : std::sqrt(nb);
+    P.nc = w->st.scale_iters > 0 ? std::sqrt(nc0) : std::sqrt(nc);
+    if (w->st.scale_iters > 0) {
+        // residuals in the original units: rows times 1 / D, columns times 1 / E
+        std::vector<double> rs(m), cs_(nx);
+        for (int i = 0; i < m; ++i) rs[i] = 1.0 / Dfull[i];
+        for (int e = 0; e < nx; ++e) cs_[e] = 1.0 / w->Ecol[e];
+        P.rsc64 = up_d(rs);
+        P.csc64 = up_d(cs_);
+    }
     P.u64 = M.alloc<double>(nx + m);
     P.v64 = M.alloc<double>(nx);
     P.u32 = M.alloc<float>(nx + m);
@@ -659,6 +748,24 @@ void svec_to_full(const sos_work *w, const std::vector<double> &s, double scale,
     }
 }
 
+// iterate of the equilibrated problem (lower triangles, u = (x^, y^), v = z^) <-> original units
+void to_original(const sos_work *w, std::vector<double> &u, std::vector<double> &v) {
+    if (w->st.scale_iters <= 0) return;
+    for (int e = 0; e < w->nx; ++e) {
+        u[e] *= w->Ecol[e];
+        v[e] /= w->Ecol[e];
+    }
+    for (int i = 0; i < w->m; ++i) u[w->nx + i] *= w->Drow[i];
+}
+void to_internal(const sos_work *w, std::vector<double> &u, std::vector<double> &v) {
+    if (w->st.scale_iters <= 0) return;
+    for (int e = 0; e < w->nx; ++e) {
+        u[e] /= w->Ecol[e];
+        v[e] *= w->Ecol[e];
+    }
+    for (int i = 0; i < w->m; ++i) u[w->nx + i] /= w->Drow[i];
+}
+
 void fetch_state(const sos_work *w, std::vector<double> &u, std::vector<double> &v, double tk[2]) {
     const int nu = w->nx + w->m, nv = w->nx;
     u.resize(nu);
@@ -821,6 +928,7 @@ int sos_warm_start(sos_work *w, const double *x, const double *y, const double *
             v[e] = tau * zs[e];
         }
         for (int i = 0; i < w->m; ++i) u[w->nx + i] = tau * y[i];
+        to_internal(w, u, v);
         const double tk[2] = {tau, kappa};
         push_state(w, u, v, tk, true);
     });
@@ -833,6 +941,7 @@ int sos_get_solution(const sos_work *w, double *x, double *y, double *z) {
         double tk[2];
         fetch_state(w, u, v, tk);
         if (!(tk[0] > 0.0)) throw Status(SOS_E_STATE, "tau == 0: no solution to normalise (certificate state)");
+        to_original(w, u, v);
         const double s = 1.0 / tk[0];
         if (x) svec_to_full(w, u, s, x);
         if (z) svec_to_full(w, v, s, z);
@@ -847,6 +956,7 @@ int sos_get_iterate(const sos_work *w, double *uo, double *vo) {
         std::vector<double> u, v;
         double tk[2];
         fetch_state(w, u, v, tk);
+        to_original(w, u, v);
         const int n = w->n_full, m = w->m;
         svec_to_full(w, u, 1.0, uo);
         for (int i = 0; i < m; ++i) uo[n + i] = u[w->nx + i];
@@ -876,6 +986,7 @@ int sos_set_iterate(sos_work *w, const double *uo, const double *vo) {
             v[e] = vs[e];
         }
         for (int i = 0; i < m; ++i) u[w->nx + i] = uo[n + i];
+        to_internal(w, u, v);
         const double tk[2] = {uo[n + m], vo[n + m]};
         push_state(w, u, v, tk);
     });

@@ -50,6 +50,9 @@ struct ProbDesc {
     const double *c64; const float *c32;
     const double *cw64; const float *cw32;
     const double *wgt64;
+    // equilibrated problems: 1 / D per row and 1 / E per column, so that residuals and
+    // certificates are measured in the original units (null: no equilibration)
+    const double *rsc64, *csc64;
     double eta, nb, nc;
 
     // iterate

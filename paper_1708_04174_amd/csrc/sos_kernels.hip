@@ -1185,10 +1185,14 @@ __device__ __noinline__ int residual_phase(const ProbDesc &P, double tol, double
     for (int a = tid; a < m; a += NT) {
         double ax = 0.0;
         for (int e = P.rowptr[a]; e < P.rowptr[a + 1]; ++e) ax += P.val64[e] * (double)u[P.colidx[e]];
-        const double rp = ax - P.b64[a] * tau;
+        acc[2] += P.b64[a] * (double)u[nx + a];
+        double rp = ax - P.b64[a] * tau;
+        if (P.rsc64) {   // equilibrated: rows back in the original units
+            rp *= P.rsc64[a];
+            ax *= P.rsc64[a];
+        }
         acc[0] += rp * rp;
         acc[1] += ax * ax;
-        acc[2] += P.b64[a] * (double)u[nx + a];
     }
     // columns: |A^T y + z - c tau|^2 and |A^T y + z|^2 folded into acc[3] / second pass, c^T xi
     double acc2[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1201,8 +1205,12 @@ __device__ __noinline__ int residual_phase(const ProbDesc &P, double tol, double
             const int j = -2 - r;
             for (int i = P.fptr[j]; i < P.fptr[j + 1]; ++i) aty += P.fval64[i] * (double)u[nx + P.frow[i]];
         }
-        const double g = aty + (double)v[e];
-        const double rd = g - P.c64[e] * tau;
+        double g = aty + (double)v[e];
+        double rd = g - P.c64[e] * tau;
+        if (P.csc64) {   // equilibrated: columns back in the original units
+            rd *= P.csc64[e];
+            g *= P.csc64[e];
+        }
         const double wg = P.wgt64[e];
         acc2[0] += wg * rd * rd;
         acc2[1] += wg * g * g;

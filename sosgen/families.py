@@ -42,15 +42,52 @@ def pop_from_poly(p: Poly, half_degree: int, meta: Optional[dict] = None) -> Con
     return build_sos_sdp(n, 1, [-1.0], [eq], md)
 
 
-def ball_pop_from_poly(p: Poly, half_degree: int, meta: Optional[dict] = None) -> ConicProblem:
-    """max gamma s.t. p - gamma = s0 + s1 (1 - |x|^2); s0 of degree 2d, s1 of degree 2d-2."""
+def ball_form_widths(n: int, half_degree: int):
+    """Low-rank widths k (columns of A_f: free variables plus non-orthogonal columns, counted
+    over lower triangles) of the ball POP's two forms, and the number of rows m of the weighted
+    form.  Weighted (Section VI): gamma plus the multiplier's Gram block, 1 + N1 (N1 + 1) / 2
+    with N1 = C(n + d - 1, d - 1).  Extra polynomial (Section II-B): gamma plus the coefficients
+    of r(x), 1 + C(n + 2d - 2, 2d - 2)."""
+    N1 = comb(n + half_degree - 1, half_degree - 1)
+    return 1 + N1 * (N1 + 1) // 2, 1 + comb(n + 2 * half_degree - 2, 2 * half_degree - 2), \
+        comb(n + 2 * half_degree, 2 * half_degree)
+
+
+def ball_pop_from_poly(p: Poly, half_degree: int, meta: Optional[dict] = None,
+                       form: str = "weighted") -> ConicProblem:
+    """max gamma s.t. p - gamma = s0 + s1 (1 - |x|^2); s0 of degree 2d, s1 of degree 2d-2.
+
+    form "weighted": the multiplier s1 enters as a weighted Gram block (Section VI): its columns
+    carry several nonzeros and join A_f.  form "extra": the multiplier is an extra polynomial
+    r(x) with free coefficients, p - gamma - r (1 - |x|^2) = s0 and r = s1 (Section II-B), so every
+    Gram column has one nonzero and A_f is gamma plus r's coefficients.  form "auto": the form
+    with the smaller A_f width (the matrix inversion lemma's small system; Section VI's advantage
+    condition compares that width with m), the weighted one on a tie (it has fewer rows)."""
     n = p.n
     ball = Poly.const(n, 1.0) - _sum_sq(n)
-    eq = SOSEquation(row_degree=2 * half_degree, g0=p, g={0: Poly.const(n, 1.0)},
-                     blocks=[(half_degree, Poly.const(n, 1.0)), (half_degree - 1, ball)])
-    md = {"kind": "ball_pop", "gamma_index": 0, "n_vars": n, "half_degree": half_degree}
+    kw, ke, m = ball_form_widths(n, half_degree)
+    if form == "auto":
+        form = "weighted" if kw <= ke else "extra"
+    md = {"kind": "ball_pop", "gamma_index": 0, "n_vars": n, "half_degree": half_degree, "form": form,
+          "k_weighted": kw, "k_extra": ke, "m_weighted": m}
     md.update(meta or {})
-    return build_sos_sdp(n, 1, [-1.0], [eq], md)
+    if form == "weighted":
+        eq = SOSEquation(row_degree=2 * half_degree, g0=p, g={0: Poly.const(n, 1.0)},
+                         blocks=[(half_degree, Poly.const(n, 1.0)), (half_degree - 1, ball)])
+        return build_sos_sdp(n, 1, [-1.0], [eq], md)
+    if form != "extra":
+        raise ValueError(f"unknown form {form!r}")
+    rmons = monomials(n, 2 * half_degree - 2)
+    t = 1 + len(rmons)
+    g1 = {0: Poly.const(n, 1.0)}
+    g2 = {}
+    for k, e in enumerate(rmons):
+        mk = Poly(n, {tuple(e): 1.0})
+        g1[1 + k] = mk * ball          # p - gamma - sum_k r_k m_k (1 - |x|^2) = s0
+        g2[1 + k] = mk.scale(-1.0)     # 0 - sum_k r_k (-m_k) = r = s1
+    eq1 = SOSEquation(row_degree=2 * half_degree, g0=p, g=g1, blocks=[(half_degree, Poly.const(n, 1.0))])
+    eq2 = SOSEquation(row_degree=2 * half_degree - 2, g0=Poly(n), g=g2, blocks=[(half_degree - 1, Poly.const(n, 1.0))])
+    return build_sos_sdp(n, t, [-1.0] + [0.0] * (t - 1), [eq1, eq2], md)
 
 
 # ---------------------------------------------------------------- quartic POPs
@@ -132,13 +169,14 @@ def pop_batch_member(seed: int, scaled: bool = True) -> ConicProblem:
                                 "gamma_scale": s ** 4})
 
 
-def pop_ball(n: int, seed: int) -> ConicProblem:
-    """Quartic POP on the unit ball, N(0,1) on every monomial of degree <= 4, weighted multiplier."""
+def pop_ball(n: int, seed: int, form: str = "weighted", half_degree: int = 2) -> ConicProblem:
+    """POP on the unit ball, N(0,1) on every monomial of degree <= 4 (quartic p), relaxation of
+    order 2d = 2 half_degree; the multiplier in the given form (see ball_pop_from_poly)."""
     rng = np.random.default_rng(seed)
     mons = monomials(n, 4)
     coef = rng.standard_normal(len(mons))
     p = Poly(n, dict(zip(mons, coef)))
-    return ball_pop_from_poly(p, 2, {"family": "pop_ball", "seed": seed})
+    return ball_pop_from_poly(p, half_degree, {"family": "pop_ball", "seed": seed}, form=form)
 
 
 def example_pop_poly(n: int) -> Poly:
