@@ -193,6 +193,16 @@ int sos_get_iterate(const sos_work *w, double *u, double *v);
    of v and the free part of z must be zero, as every iterate of the method has. */
 int sos_set_iterate(sos_work *w, const double *u, const double *v);
 
+/* Eigen-decomposition of PSD block `block` of the current solution, for post-processing:
+   dual = 0 factors X = xi / tau (the Gram matrix: p - gamma = sum_j evals[j] (v_j^T m(x))^2,
+   the SOS decomposition of Section I and Section II-C), dual = 1 factors Z = z / tau (for a
+   POP relaxation with cost -gamma, the moment matrix of the dual).  evals: N entries (Rayleigh
+   quotients v_j^T W v_j, signed, in the order the eigensolver leaves them); evecs: N x N,
+   column-major, orthonormal columns v_j.  Runs the library's FP64 Jacobi eigensolver on the
+   device (one workgroup; a temporary device buffer of N^2 + N doubles is allocated and freed).
+   SOS_E_INVAL for a bad block index or dual; SOS_E_STATE if tau == 0. */
+int sos_psd_factor(sos_work *w, int32_t block, int32_t dual, double *evals, double *evecs);
+
 /* Message for the last error on w (or on the last failed sos_setup when w is NULL). */
 const char *sos_last_error(const sos_work *w);
 

@@ -23,7 +23,7 @@ SOS_PART_PAPER, SOS_PART_COLUMNS = 0, 1
 STATUS_NAMES = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_infeasible", 4: "max_iters"}
 
 EXPORTED = ["sos_default_settings", "sos_setup", "sos_step", "sos_step_static", "sos_solve", "sos_warm_start",
-            "sos_get_solution", "sos_get_iterate", "sos_set_iterate", "sos_last_error", "sos_free",
+            "sos_get_solution", "sos_get_iterate", "sos_set_iterate", "sos_psd_factor", "sos_last_error", "sos_free",
             "sos_batch_setup", "sos_batch_solve", "sos_batch_reset", "sos_batch_last_ms",
             "sos_batch_phase_ms", "sos_batch_free", "sos_layout_size", "sos_batch_warm_start",
             "sos_batch_export_solutions", "sos_mlp_create", "sos_mlp_num_params", "sos_mlp_set_params",
@@ -95,6 +95,7 @@ def load():
     lib.sos_get_solution.argtypes = [vp, P(C.c_double), P(C.c_double), P(C.c_double)]
     lib.sos_get_iterate.argtypes = [vp, P(C.c_double), P(C.c_double)]
     lib.sos_set_iterate.argtypes = [vp, P(C.c_double), P(C.c_double)]
+    lib.sos_psd_factor.argtypes = [vp, C.c_int32, C.c_int32, P(C.c_double), P(C.c_double)]
     lib.sos_last_error.argtypes = [vp]
     lib.sos_last_error.restype = C.c_char_p
     lib.sos_free.argtypes = [vp]
@@ -166,9 +167,10 @@ def sos_default_settings(**overrides) -> sos_settings:
 class Work:
     """Owns one sos_work handle; the arrays it describes stay readable via the methods below."""
 
-    def __init__(self, handle: C.c_void_p, n: int, m: int):
+    def __init__(self, handle: C.c_void_p, n: int, m: int, psd_dims=()):
         self.handle = handle
         self.n, self.m = n, m
+        self.psd_dims = list(psd_dims)
 
     def __del__(self):
         try:
@@ -203,7 +205,7 @@ def sos_setup(A, b, c, n_free: int, psd_dims: Sequence[int], settings: Optional[
     rc = lib.sos_setup(C.byref(csc), _dptr(b), _dptr(c), C.byref(cone),
                        C.byref(settings) if settings is not None else None, st, C.byref(h))
     _check(rc, None)
-    return Work(h, A.shape[1], A.shape[0])
+    return Work(h, A.shape[1], A.shape[0], [int(x) for x in Ns])
 
 
 def setup_problem(prob, settings: Optional[sos_settings] = None, stream=None) -> Work:
@@ -257,6 +259,15 @@ def sos_set_iterate(w: Work, u, v) -> None:
     if u.shape != (w.n + w.m + 1,) or v.shape != (w.n + w.m + 1,):
         raise ValueError("iterate has the wrong shape")
     _check(load().sos_set_iterate(w.handle, _dptr(u), _dptr(v)), w.handle)
+
+
+def sos_psd_factor(w: Work, block: int, dual: bool = False):
+    """(evals (N), evecs (N x N)) of block `block` of X = xi / tau, or of Z = z / tau if dual."""
+    N = int(w.psd_dims[block]) if 0 <= block < len(w.psd_dims) else 1   # a bad index: the library says so
+    lam = np.empty(N)
+    vec = np.empty(N * N)
+    _check(load().sos_psd_factor(w.handle, int(block), int(bool(dual)), _dptr(lam), _dptr(vec)), w.handle)
+    return lam, vec.reshape(N, N, order="F")
 
 
 def sos_free(w: Work) -> None:

@@ -992,6 +992,33 @@ int sos_set_iterate(sos_work *w, const double *uo, const double *vo) {
     });
 }
 
+int sos_psd_factor(sos_work *w, int32_t block, int32_t dual, double *evals, double *evecs) {
+    if (!w || !evals || !evecs) return SOS_E_INVAL;
+    return guarded(w, [&] {
+        if (block < 0 || block >= (int)w->N.size()) throw Status(SOS_E_INVAL, "block index out of range");
+        if (dual != 0 && dual != 1) throw Status(SOS_E_INVAL, "dual must be 0 (X) or 1 (Z)");
+        const int N = w->N[block];
+        set_active(w, true);   // the kernel reads the FP64 iterate
+        double tk[2];
+        hip_check(hipMemcpyAsync(tk, w->desc.tk, sizeof(tk), hipMemcpyDeviceToHost, w->stream), "copy");
+        hip_check(hipStreamSynchronize(w->stream), "sync");
+        if (!(tk[0] > 0.0)) throw Status(SOS_E_STATE, "tau == 0: no solution to factor (certificate state)");
+        DeviceArena tmp;
+        double *d_val = tmp.alloc<double>(N), *d_vec = tmp.alloc<double>((size_t)N * N);
+        if (!d_val || !d_vec) throw Status(SOS_E_NOMEM, "hipMalloc failed");
+        RunParams rp = single_params(w, RUN_STEP, 0, 0, w->st.tol);
+        if (sos_launch_psd_factor(w->threads, rp, block, dual, d_val, d_vec, w->stream))
+            throw Status(SOS_E_HIP, "factor launch failed");
+        hip_check(hipMemcpyAsync(evals, d_val, sizeof(double) * N, hipMemcpyDeviceToHost, w->stream), "copy");
+        hip_check(hipMemcpyAsync(evecs, d_vec, sizeof(double) * N * N, hipMemcpyDeviceToHost, w->stream), "copy");
+        hip_check(hipStreamSynchronize(w->stream), "sync");
+        if (w->st.scale_iters > 0) {   // one factor e per block: X = e X^, Z = Z^ / e
+            const double e = w->Ecol[w->off_svec[block]];
+            for (int j = 0; j < N; ++j) evals[j] = dual ? evals[j] / e : evals[j] * e;
+        }
+    });
+}
+
 const char *sos_last_error(const sos_work *w) { return w ? w->err.c_str() : g_setup_error.c_str(); }
 
 void sos_free(sos_work *w) {

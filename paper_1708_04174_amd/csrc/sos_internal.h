@@ -122,4 +122,8 @@ int sos_launch_warm_start(int fp64, int threads, int grid, const RunParams &rp, 
 // Device address of the static scratch (SOS_STATIC_SCRATCH_BYTES) on the current device,
 // looked up once per device; 0 on success, -4 if the lookup failed.
 int sos_static_scratch(void **ptr);
+// eigen-decomposition of PSD block blk of problem 0's solution (dual: of z instead of xi), one
+// workgroup; evals (N) and evecs (N x N, column-major) device arrays
+int sos_launch_psd_factor(int threads, const RunParams &rp, int blk, int dual, double *evals, double *evecs,
+                          void *stream);
 int sos_launch_export(int fp64, const ProbDesc *probs, int count, float *out, long long ld, int max_len, void *stream);

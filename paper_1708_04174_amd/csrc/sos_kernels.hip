@@ -1578,6 +1578,66 @@ __global__ __launch_bounds__(NT) void warm_start_kernel(RunParams rp, const floa
     }
 }
 
+// Eigen-decomposition of one PSD block of the current solution, X = xi / tau (dual = 0) or
+// Z = z / tau (dual = 1), by the projection's own Jacobi eigensolver (cold start, FP64, full
+// accuracy): eigenvectors column-major into evecs (N x N), eigenvalues as Rayleigh quotients
+// v_j^T W v_j (signed) into evals.  One workgroup on problem 0 of rp.  W is staged in the
+// eigensolver scratch Tm, which a cold projection does not use; the projection's own output
+// goes to the work area.
+template <int NT>
+__global__ __launch_bounds__(NT) void psd_factor_kernel(RunParams rp, int blk, int dual, double *__restrict__ evals,
+                                                      double *__restrict__ evecs) {
+    __shared__ int s_flag;
+    __shared__ int s_sweeps;
+    __shared__ double s_red[4 * (NT / 64)];
+    extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+    typename Lds<double>::type *s_sig = as_lds<double>(dyn_lds);
+    typename Lds<double>::type *s_mat = as_lds<double>(dyn_lds + rp.lds_mat_off);
+    EigScratch sc;
+    sc.s_flag = as_lds<int>((void *)&s_flag);
+    sc.s_sweeps = as_lds<int>((void *)&s_sweeps);
+    sc.s_red = s_red;
+    sc.jtol = 0.0;
+    if (threadIdx.x == 0) s_sweeps = 0;
+    const ProbDesc &P = rp.probs[0];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr int NW = NT / 64;
+    const int off = P.blk_off[blk], N = P.blk_N[blk], ns = N * (N + 1) / 2;
+    const double inv_tau = 1.0 / P.tk[0];
+    const double *src = (dual ? P.v64 : P.u64) + off;
+    double *Tm = reinterpret_cast<double *>(rp.eig);
+    double *wout = reinterpret_cast<double *>(rp.work);
+    for (int e = tid; e < ns; e += NT) Tm[e] = src[e] * inv_tau;
+    __syncthreads();
+    double *g1 = Tm + (long long)P.nmax * P.nmax, *g2 = g1 + (long long)P.nmax * P.nmax;
+    if (N <= rp.rows_nmax && N >= rp.rows_nmin)
+        project_block_rows<double, NT>(Tm, wout, N, evecs, false, s_mat, Tm, sc, rp.max_sweeps);
+    else if (N <= rp.lds_nmax)
+        project_block<double, NT>(Tm, wout, N, evecs, false, s_mat, s_mat + (long long)N * lds_ld(N), lds_ld(N), Tm,
+                                  s_sig, sc, rp.max_sweeps, lanes_per_pair(rp, N));
+    else if (N <= rp.lds_nmax_g)
+        project_block<double, NT>(Tm, wout, N, evecs, false, s_mat, g1, N, Tm, s_sig, sc, rp.max_sweeps,
+                                  lanes_per_pair(rp, N));
+    else
+        project_block<double, NT>(Tm, wout, N, evecs, false, g1, g2, N, Tm, s_sig, sc, rp.max_sweeps,
+                                  lanes_per_pair(rp, N));
+    // Rayleigh quotients with W read from the iterate (the staged copy was overwritten)
+    for (int j = wid; j < N; j += NW) {
+        const double *vj = evecs + (long long)j * N;
+        double acc = 0.0;
+        for (int i = lane; i < N; i += 64) {
+            double wv = 0.0;
+            for (int k = 0; k < N; ++k) {
+                const int a = i > k ? i : k, b = i > k ? k : i;
+                wv += src[svec_idx(a, b, N)] * vj[k];
+            }
+            acc += vj[i] * wv;
+        }
+        acc = wave_allsum(acc);
+        if (lane == 0) evals[j] = acc * inv_tau;
+    }
+}
+
 // rows of out (ld apart): [xi / tau (nx) | y / tau (m)] of every problem, FP32, internal layout
 template <typename T>
 __global__ void export_solution(const ProbDesc *probs, int count, float *out, long long ld) {
@@ -1815,6 +1875,35 @@ int sos_static_scratch(void **ptr) {
     }
     *ptr = addr[dev];
     return 0;
+}
+
+int sos_launch_psd_factor(int threads, const RunParams &rp_in, int blk, int dual, double *evals, double *evecs,
+                          void *stream) {
+    RunParams rp = rp_in;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    size_t lds = 0;
+    (void)hipGetLastError();
+#define SOS_PF(NTT)                                                                                               \
+    {                                                                                                            \
+        lds_layout<double>(rp.eig_ld, rp.lds_budget, NTT / 64, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds,   \
+                           rp.eig_wave, rp.rows_nmax);                                                           \
+        if (lds > 64 * 1024) {                                                                                   \
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&psd_factor_kernel<NTT>),                    \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                     \
+            (void)hipGetLastError();                                                                             \
+        }                                                                                                        \
+        hipLaunchKernelGGL((psd_factor_kernel<NTT>), dim3(1), dim3(NTT), lds, st, rp, blk, dual, evals, evecs);   \
+    }
+    switch (threads) {
+        case 64: SOS_PF(64) break;
+        case 128: SOS_PF(128) break;
+        case 256: SOS_PF(256) break;
+        case 512: SOS_PF(512) break;
+        case 1024: SOS_PF(1024) break;
+        default: return -1;
+    }
+#undef SOS_PF
+    return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
 int sos_launch_export(int fp64, const ProbDesc *probs, int count, float *out, long long ld, int max_len, void *stream) {
