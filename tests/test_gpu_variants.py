@@ -11,6 +11,7 @@ import pytest
 
 from oracle.admm import Oracle
 from sosgen import families as F
+from sosgen import matrix_sos as MS
 
 pytestmark = pytest.mark.gpu
 
@@ -100,3 +101,28 @@ def test_step_parity_ball_pop_forms(B, form):
     w.free()
     assert inf["k_lowrank"] == prob.meta["k_" + form]
     _parity(B, prob, [1, 5, 25], tag=f"ball n3 2d6 {form}")
+
+
+MATRIX = {"n2_r3": lambda: MS.matrix_pop(2, 3, 2), "n3_r2": lambda: MS.matrix_pop(3, 2, 1)}
+
+
+@pytest.mark.parametrize("name", list(MATRIX))
+def test_step_parity_matrix_sos(B, name):
+    # matrix-valued SOS (Section V): one Gram block of size r N, every Y column in A_s
+    prob = MATRIX[name]()
+    _parity(B, prob, [1, 4, 30], tag=f"matrix sos {name}")
+
+
+@pytest.mark.parametrize("name", list(MATRIX))
+def test_solve_parity_matrix_sos(B, name):
+    prob = MATRIX[name]()
+    r = Oracle.from_problem(prob).solve(tol=1e-6, max_iters=20000)
+    w = B.setup_problem(prob, B.sos_default_settings(tol=1e-6, max_iters=20000))
+    inf = B.sos_solve(w)
+    x, _, _ = B.sos_get_solution(w)
+    w.free()
+    print(f"[variants] matrix sos {name}: gpu {inf['status_name']} {inf['iters']} gamma {x[0]:.9f} (k {inf['k_lowrank']}); "
+          f"oracle {r.status_name} {r.iters} gamma {r.x[0]:.9f}", flush=True)
+    assert inf["status"] == r.status == 1 and inf["k_lowrank"] == 1
+    assert inf["iters"] == r.iters
+    assert abs(x[0] - r.x[0]) <= 1e-6 * max(1.0, abs(r.x[0]))
