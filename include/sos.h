@@ -97,8 +97,15 @@ typedef struct {
                                 lane-group form for N < 96, 8 lanes per column pair for N >= 64,
                                 the rows-over-wavefronts form from N = 96 for blocks that fit in
                                 LDS), 1 = rows form for every block that fits in LDS, 2 = lane-group
-                                form for every block.  Batches take theirs from the schedule.
-                                Out of 0..2: SOS_E_INVAL. */
+                                form for every block, 3 = the multi-workgroup form for every block.
+                                In SOS_FP64, eig_form 0 also runs a single problem whose largest
+                                block has N >= 128 as one cooperative launch over several workgroups:
+                                workgroup 0 takes the affine step and the residual checks, all of
+                                them a block one-sided Jacobi (column blocks of up to 8 columns, one
+                                workgroup per pair of blocks and block round, a grid barrier per
+                                round) and the MFMA products (a solve with warm_budget > 0 stays on
+                                one workgroup).  Batches take theirs from the schedule.
+                                Out of 0..3: SOS_E_INVAL. */
     int32_t warm_budget;     /* 0: a warm-started solve keeps its start to the end.  > 0: a solve that
                                 starts from sos_warm_start / sos_batch_warm_start and has neither
                                 converged after warm_budget iterations nor kept tau > 0 at a residual
@@ -166,7 +173,9 @@ int sos_step(sos_work *w, int32_t iters, sos_info *info);
    or other allocating call is made; the handle's device must be current.  The array keeps
    the last call's contents; each call clears what must start at zero (the queue counter)
    with a kernel, and every other byte is written before it is read.  Calls that overlap on
-   one GPU share the array and race: serialise them (one stream, or host ordering).
+   one GPU share the array and race: serialise them (one stream, or host ordering).  It always
+   runs the one-workgroup form (the multi-workgroup form of eig_form 0 / 3 keeps its scratch on
+   the handle), so it matches sos_step where sos_step runs that form too.
    A problem needing more than 4 MiB of scratch (about 3 N^2 + m + n_x doubles, N the
    largest block) is rejected with SOS_E_INVAL and a message; then nothing is launched. */
 int sos_step_static(sos_work *w, int32_t iters, sos_info *info);

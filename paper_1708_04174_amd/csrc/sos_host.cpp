@@ -35,6 +35,11 @@ constexpr int kRowsNmin = 96;
 // Lyapunov batch, and save about one sweep per projection against 16 eps.
 constexpr double kMixedJacobiTol64 = 1e-7;
 constexpr int kLanesPerPair[7] = {16, 16, 8, 8, 16, 16, 16};
+// FP64 single solves take the multi-workgroup (cooperative) path from this largest block size on
+// (eig_form 0); eig_form 3 takes it for every block
+constexpr int kCoopNmin = 128;
+// columns per Jacobi block of the multi-workgroup eigensolver (fewer when LDS is short)
+constexpr int kCoopBcols = 8;
 // mixed form: the FP32 phase hands over after this many residual checks without a 10 % gain.
 // An FP32-stored iterate has a residual floor of about eps_32 |A| |y| / tau (above 1e-4 on the
 // Lyapunov family), so the hand-over should come soon after the floor is reached.
@@ -110,6 +115,11 @@ struct sos_work {
     int eig_ld = 0;
     int threads = 256;
     bool active64 = true;     // which copy of (u, v) holds the current iterate
+    // multi-workgroup path (FP64 single solves with a large block): cooperative grid, scratch
+    bool use_coop = false;
+    int coop_grid = 0, coop_bcols = 0, coop_threads = 512;
+    double *d_coop_scr = nullptr;
+    CoopCtl *d_ctl = nullptr;
     // equilibration: the iteration runs on D A E; x = E x^, y = D y^, z = z^ / E
     std::vector<double> Drow; // m
     std::vector<double> Ecol; // nx (internal columns)
@@ -169,7 +179,7 @@ void check_settings(const sos_settings &s) {
         throw Status(SOS_E_INVAL, "block_threads must be 0 or a power of two in 64..1024");
     if (s.precision == SOS_FP32_MIXED && s.polish_iters < 1) throw Status(SOS_E_INVAL, "polish_iters >= 1 required");
     if (s.warm_budget < 0) throw Status(SOS_E_INVAL, "warm_budget must be >= 0");
-    if (s.eig_form < 0 || s.eig_form > 2) throw Status(SOS_E_INVAL, "eig_form must be 0, 1 or 2");
+    if (s.eig_form < 0 || s.eig_form > 3) throw Status(SOS_E_INVAL, "eig_form must be 0, 1, 2 or 3");
     if (s.scale_iters < 0 || s.scale_iters > 1000) throw Status(SOS_E_INVAL, "scale_iters must be in 0..1000");
 }
 
@@ -237,12 +247,14 @@ void equilibrate(const sos_csc *A, const sos_cone *K, int passes, std::vector<do
     }
 }
 
+void setup_coop(sos_work *w);
+
 void build(sos_work *w, const sos_csc *A, const double *b, const double *c, const sos_cone *K) {
     if (!A || !b || !c || !K || !A->colptr || (!A->rowind && A->colptr[A->n] > 0))
         throw Status(SOS_E_INVAL, "null argument");
     const int m = A->m, n = A->n;
     if (m < 0 || n < 1 || K->n_free < 0 || K->n_psd < 0 || K->n_psd > SOS_MAX_BLOCKS)
-        throw Status(SOS_E_INVAL, "bad dimensions (at most 8 PSD blocks)");
+        throw Status(SOS_E_INVAL, "bad dimensions (at most 64 PSD blocks)");
     long long ncheck = K->n_free;
     for (int j = 0; j < K->n_psd; ++j) {
         if (K->N[j] < 1 || K->N[j] > 2048) throw Status(SOS_E_INVAL, "PSD block size must be in 1..2048");
@@ -353,7 +365,6 @@ void build(sos_work *w, const sos_csc *A, const double *b, const double *c, cons
         }
     }
     const int k = (int)fcols.size();
-    if (k > SOS_KMAX_LDS) throw Status(SOS_E_INVAL, "low-rank part wider than 1024 columns is not supported");
     w->k = k;
     std::vector<double> colval(nx, 0.0), d(m, 1.0);
     for (int e = 0; e < nx; ++e) {
@@ -592,15 +603,56 @@ void build(sos_work *w, const sos_csc *A, const double *b, const double *c, cons
     hip_check(hipMemcpyAsync(w->d_order, &zero, sizeof(int), hipMemcpyHostToDevice, st), "hipMemcpyAsync");
     // per-workgroup areas for a single-problem launch
     w->eig_ld = std::max(w->nmax, 1);
-    w->work_stride = (long long)(((m + 63) & ~63) + nx + 64) * sizeof(double);
+    w->work_stride = (long long)(((m + 63) & ~63) + nx + 64 + sos_work_tail_doubles(k)) * sizeof(double);
     w->eig_stride = (long long)3 * w->eig_ld * std::max(w->nmax, 1) * sizeof(double) + 256;
     w->d_work = M.alloc<char>(w->work_stride);
     w->d_eig = M.alloc<char>(w->eig_stride);
     if (!w->d_work || !w->d_eig) throw Status(SOS_E_NOMEM, "hipMalloc failed");
     hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
     w->active64 = true;
+    setup_coop(w);
     hip_check(hipEventCreate(&w->ev0), "hipEventCreate");
     hip_check(hipEventCreate(&w->ev1), "hipEventCreate");
+}
+
+RunParams single_params(sos_work *w, int mode, int iters, int min_iters, double tol);
+
+// Multi-workgroup path: FP64, a block of at least kCoopNmin (eig_form 0) or any (eig_form 3), a
+// device with cooperative launches.  Column blocks of up to kCoopBcols columns, as many as LDS
+// holds (two blocks of G and V, FP64); one workgroup per pair of blocks.
+void setup_coop(sos_work *w) {
+    w->use_coop = false;
+    if (w->st.precision != SOS_FP64 || w->N.empty()) return;
+    if (!(w->st.eig_form == 3 || (w->st.eig_form == 0 && w->nmax >= kCoopNmin))) return;
+    const int thr = (w->threads == 256 || w->threads == 512) ? w->threads : 512;
+    RunParams rp = single_params(w, RUN_STEP, 0, 0, w->st.tol);
+    int bcols = kCoopBcols;
+    while (bcols > 1 && (long long)sizeof(double) * 4 * bcols * w->nmax > kLdsBudget) --bcols;
+    const int gmax = sos_coop_max_grid(thr, rp, bcols);
+    if (gmax < 1) {
+        if (w->st.eig_form == 3) throw Status(SOS_E_INVAL, "multi-workgroup eigensolver unavailable on this device/shape");
+        return;
+    }
+    const int nb = (w->nmax + bcols - 1) / bcols;
+    const int pairs = (nb + (nb & 1)) / 2;
+    w->coop_grid = std::max(1, std::min(gmax, pairs));
+    w->coop_bcols = bcols;
+    w->coop_threads = thr;
+    const size_t nm = (size_t)w->nmax;
+    w->d_coop_scr = w->mem.alloc<double>(3 * nm * nm + nm + SOS_COOP_MAX_WG);
+    w->d_ctl = w->mem.alloc<CoopCtl>(1);
+    if (!w->d_coop_scr || !w->d_ctl) throw Status(SOS_E_NOMEM, "hipMalloc failed");
+    w->use_coop = true;
+}
+
+// the FP64 iterations of a single solve over the cooperative grid; checks the barrier's flag
+void run_coop(sos_work *w, const RunParams &rp) {
+    if (sos_launch_admm_coop(w->coop_threads, w->coop_grid, rp, w->d_ctl, w->d_coop_scr, w->coop_bcols, w->stream))
+        throw Status(SOS_E_HIP, "cooperative launch failed");
+    CoopCtl c;
+    hip_check(hipMemcpyAsync(&c, w->d_ctl, sizeof(c), hipMemcpyDeviceToHost, w->stream), "copy");
+    hip_check(hipStreamSynchronize(w->stream), "sync");
+    if (c.err) throw Status(SOS_E_HIP, "multi-workgroup launch: a grid barrier wait timed out");
 }
 
 RunParams single_params(sos_work *w, int mode, int iters, int min_iters, double tol) {
@@ -695,7 +747,12 @@ void step_impl(sos_work *w, int32_t iters, sos_info *info, bool static_scratch) 
     }
     set_active(w, fp64);
     hip_check(hipEventRecord(w->ev0, w->stream), "event");
-    run_single(w, fp64, rp);
+    if (fp64 && w->use_coop && !static_scratch) {
+        if (sos_launch_admm_coop(w->coop_threads, w->coop_grid, rp, w->d_ctl, w->d_coop_scr, w->coop_bcols, w->stream))
+            throw Status(SOS_E_HIP, "cooperative launch failed");
+    } else {
+        run_single(w, fp64, rp);
+    }
     hip_check(hipEventRecord(w->ev1, w->stream), "event");
     double o[SOS_OUT_N];
     hip_check(hipMemcpyAsync(o, w->desc.out, sizeof(o), hipMemcpyDeviceToHost, w->stream), "copy");
@@ -703,6 +760,11 @@ void step_impl(sos_work *w, int32_t iters, sos_info *info, bool static_scratch) 
     float ms = 0.f;
     hip_check(hipEventElapsedTime(&ms, w->ev0, w->ev1), "event");
     w->last_ms = ms;
+    if (fp64 && w->use_coop && !static_scratch) {
+        CoopCtl c;
+        hip_check(hipMemcpy(&c, w->d_ctl, sizeof(c), hipMemcpyDeviceToHost), "copy");
+        if (c.err) throw Status(SOS_E_HIP, "multi-workgroup launch: a grid barrier wait timed out");
+    }
     read_info(w, o, info, iters, 0);
 }
 
@@ -877,7 +939,8 @@ int sos_solve(sos_work *w, sos_info *info) {
             set_active(w, true);
             RunParams r = single_params(w, RUN_SOLVE, w->st.max_iters, 0, w->st.tol);
             r.warm_budget = w->st.warm_budget;
-            run_single(w, 1, r);
+            if (w->use_coop && r.warm_budget == 0) run_coop(w, r);
+            else run_single(w, 1, r);
             hip_check(hipMemcpyAsync(o, w->desc.out, sizeof(o), hipMemcpyDeviceToHost, w->stream), "copy");
             hip_check(hipStreamSynchronize(w->stream), "sync");
             total = (int)o[SOS_OUT_ITERS];
@@ -1078,12 +1141,14 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         hip_check(hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking), "hipStreamCreate");
         std::vector<ProbDesc> descs(count);
         int mmax = 0, nxmax = 0, nmax = 1;
+        long long tailmax = 0;
         std::vector<double> cost(count);
         for (int i = 0; i < count; ++i) {
             descs[i] = probs[i]->desc;
             mmax = std::max(mmax, probs[i]->m);
             nxmax = std::max(nxmax, probs[i]->nx);
             nmax = std::max(nmax, probs[i]->nmax);
+            tailmax = std::max(tailmax, sos_work_tail_doubles(probs[i]->k));
             double c3 = 0.0;
             for (int N : probs[i]->N) c3 += (double)N * N * N;
             cost[i] = c3 + probs[i]->nx + probs[i]->m;
@@ -1106,7 +1171,7 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         const int cus = device_cu_count();
         B->grid = std::min(count, cus * B->wg_per_cu);
         B->eig_ld = nmax;
-        B->work_stride = (long long)(((mmax + 63) & ~63) + nxmax + 64) * sizeof(double);
+        B->work_stride = (long long)(((mmax + 63) & ~63) + nxmax + 64 + tailmax) * sizeof(double);
         B->eig_stride = (long long)3 * B->eig_ld * nmax * sizeof(double) + 256;
         B->d_work = B->mem.alloc<char>((size_t)B->work_stride * B->grid);
         B->d_eig = B->mem.alloc<char>((size_t)B->eig_stride * B->grid);

@@ -16,8 +16,16 @@
 #pragma once
 #include <stdint.h>
 
-#define SOS_MAX_BLOCKS 8
-#define SOS_KMAX_LDS 1024   // largest A_f width whose k-vector is kept in LDS
+#define SOS_MAX_BLOCKS 64
+#define SOS_KMAX_LDS 1024   // largest A_f width whose k-vector is kept in LDS; wider ones use the
+                            // tail of the work area (sos_work_tail_doubles)
+// doubles past the affine work vectors that a problem with an A_f of width k needs (0 if the
+// k-vector and the small solve's partial sums fit in LDS)
+static inline long long sos_work_tail_doubles(int k) {
+    if (k <= SOS_KMAX_LDS) return 0;
+    const long long kp = ((long long)k + 63) & ~63LL;
+    return kp + (kp > 1024 ? kp : 1024);
+}
 // bytes of the per-device static scratch used by sos_step_static (queue counter, affine work
 // vector and eigensolver area of one workgroup)
 #define SOS_STATIC_SCRATCH_BYTES (4 << 20)
@@ -107,6 +115,19 @@ struct RunParams {
     unsigned long long *ts; // optional [start, end] wall-clock stamps of the launch (min / max over workgroups)
 };
 
+// Control block of a cooperative (multi-workgroup) launch on one problem, in device memory.
+struct CoopCtl {
+    unsigned int count, gen;   // grid barrier: arrivals, generation
+    int err;                   // 1: a barrier wait ran past its spin limit (the launch's results are void)
+    int status;                // residual-check status broadcast by workgroup 0
+    int big[3];                // Jacobi sweep votes, by the launch's running sweep count modulo 3: the
+                               // flag reset during sweep s (that of s + 1) was last read after sweep
+                               // s - 2, before every workgroup passed the barriers of sweep s - 1
+    int pad[1];
+};
+// Largest number of workgroups of a cooperative launch (per-workgroup partial sums in the scratch).
+#define SOS_COOP_MAX_WG 1024
+
 // host-side launchers implemented in sos_kernels.hip
 int sos_launch_admm(int fp64, int threads, int grid, const RunParams &rp, void *stream);
 // the mixed form in one launch (FP32 phase, widening, FP64 phase per problem); threads 256 or
@@ -119,6 +140,15 @@ int sos_launch_reset_state(const ProbDesc *probs_dev, int count, int max_len, vo
 // grid: the number of workgroups whose scratch areas (work_stride, eig_stride apart) exist
 int sos_launch_warm_start(int fp64, int threads, int grid, const RunParams &rp, const float *pred, long long ld,
                           void *stream);
+// Multi-workgroup FP64 solve of problem 0 of rp (one cooperative launch of `grid` workgroups):
+// workgroup 0 runs the affine step and the residual checks, every workgroup the block Jacobi
+// eigensolver (column blocks of bcols columns) and the MFMA products.  scratch: 3 nmax^2 + nmax
+// doubles (G, V, W, sigma) + SOS_COOP_MAX_WG doubles of partial sums.  ctl: zeroed by the launcher.
+// Returns 0, -1 (unsupported shape), -4 (launch failed).
+int sos_launch_admm_coop(int threads, int grid, const RunParams &rp, CoopCtl *ctl, double *scratch, int bcols,
+                         void *stream);
+// Largest grid a cooperative launch of the given width may use on this device (0 if unsupported).
+int sos_coop_max_grid(int threads, const RunParams &rp, int bcols);
 // Device address of the static scratch (SOS_STATIC_SCRATCH_BYTES) on the current device,
 // looked up once per device; 0 on success, -4 if the lookup failed.
 int sos_static_scratch(void **ptr);

@@ -201,6 +201,8 @@ __device__ __noinline__ void affine_phase(const ProbDesc &P, const RunParams &rp
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     constexpr int NW = NT / 64;
     const int m = P.m, nx = P.nx, k = P.k, nfree = P.nfree;
+    // an A_f wider than the LDS k-vector: the k-vector and partial sums live past the work vectors
+    if (k > SOS_KMAX_LDS) s_z = reinterpret_cast<double *>(reinterpret_cast<char *>(wy) + sizeof(double) * ((long long)((m + 63) & ~63) + nx + 64));
     T *__restrict__ u = TS<T>::u(P);
     T *__restrict__ v = TS<T>::v(P);
     const T *__restrict__ val = TS<T>::val(P);
@@ -258,7 +260,7 @@ __device__ __noinline__ void affine_phase(const ProbDesc &P, const RunParams &rp
             if (gl == 0) s_z[j] = s;
         }
         __syncthreads();
-        schur_solve<NT>(P.Sinv, k, s_z, s_z + SOS_KMAX_LDS);
+        schur_solve<NT>(P.Sinv, k, s_z, k <= SOS_KMAX_LDS ? s_z + SOS_KMAX_LDS : s_z + ((k + 63) & ~63));
         __syncthreads();
     }
 
@@ -594,12 +596,15 @@ constexpr int kMfmaHold = 8;
 // across lanes, which keeps those reads coalesced.  hold: W occupies G's storage; every tile
 // stays in registers until all wavefronts have finished reading W (needs at most kMfmaHold
 // tiles per wavefront).  The caller ends with a barrier before G is read.
+// Tiles go to workers w0 = 0..nw-1 (wavefronts; the default is this workgroup's, a grid-wide
+// numbering spreads them over several workgroups), tile w0, w0 + nw, ...
 template <typename T, int NT, typename WP, typename VP, typename GP>
 __device__ __forceinline__ void mfma_wv(WP W, int ldw, bool wglobal, VP V, int ldv, GP G, int ldg, int N,
-                                        bool hold) {
+                                        bool hold, int w0 = -1, int nw = 0) {
     typedef typename Mma<T>::acc AC;
-    constexpr int NW = NT / 64;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wid = w0 >= 0 ? w0 : (int)(threadIdx.x >> 6);
+    const int NW = w0 >= 0 ? nw : NT / 64;
     const int li = lane & 15, lg = lane >> 4;
     const int nt = (N + 15) >> 4, ntt = nt * nt;
     for (int base = 0; base < ntt; base += NW * kMfmaHold) {
@@ -646,10 +651,12 @@ __device__ __forceinline__ void mfma_wv(WP W, int ldw, bool wglobal, VP V, int l
 // triangles by columns; vs holds w on entry).  Tiles on and below the diagonal, one per
 // wavefront at a time; step t covers V's columns k0 + l / 16.
 template <typename T, int NT, typename VP, typename SP>
-__device__ __forceinline__ void mfma_rebuild(VP V, int ldv, SP sig, int N, T *__restrict__ vs, T *__restrict__ us) {
+__device__ __forceinline__ void mfma_rebuild(VP V, int ldv, SP sig, int N, T *__restrict__ vs, T *__restrict__ us,
+                                             int w0 = -1, int nw = 0) {
     typedef typename Mma<T>::acc AC;
-    constexpr int NW = NT / 64;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wid = w0 >= 0 ? w0 : (int)(threadIdx.x >> 6);
+    const int NW = w0 >= 0 ? nw : NT / 64;
     const int li = lane & 15, lg = lane >> 4;
     const int nt = (N + 15) >> 4, ntri = nt * (nt + 1) / 2;
     for (int tile = wid; tile < ntri; tile += NW) {
@@ -1502,6 +1509,279 @@ __global__ __launch_bounds__(NT, 2) void admm_mixed(RunParams rp32, RunParams rp
     if (rp32.ts && threadIdx.x == 0) atomicMax(&rp32.ts[1], (unsigned long long)wall_clock64());
 }
 
+// ----------------------------------------------------------------------------- multi-workgroup path
+// One problem spread over a cooperative grid: a software barrier over all workgroups (they are
+// co-resident under a cooperative launch), with a bounded wait so that a missing workgroup
+// ends the launch with an error flag instead of a hang.
+__device__ __forceinline__ void grid_sync(CoopCtl *ctl) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned int g = __hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned int arrived = __hip_atomic_fetch_add(&ctl->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == gridDim.x - 1) {
+            __hip_atomic_store(&ctl->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&ctl->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            // bounded wait (about a second, far beyond any barrier of a working launch); once a wait
+            // has timed out, later barriers do not wait at all, so a broken launch still ends soon
+            long long spins = 0;
+            while (__hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g &&
+                   !__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1LL << 24)) {
+                    __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// Sum of one double per workgroup in workgroup order (the same bits in every workgroup): each
+// workgroup writes its partial into parts[blockIdx.x], then the grid barrier, then all read.
+__device__ __forceinline__ double grid_sum(double x, double *parts, CoopCtl *ctl, double *s_red1) {
+    if (threadIdx.x == 0) parts[blockIdx.x] = x;
+    grid_sync(ctl);
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int g = 0; g < (int)gridDim.x; ++g) t += __hip_atomic_load(&parts[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *s_red1 = t;
+    }
+    __syncthreads();
+    const double t = *s_red1;
+    grid_sync(ctl);   // parts may be reused right after
+    return t;
+}
+
+// Rotation of the local columns p, q (G and V in LDS, leading dimension ld) by one wavefront.
+template <typename T>
+__device__ __forceinline__ int wave_rotate_pair(typename Lds<T>::type *gp, typename Lds<T>::type *gq,
+                                                typename Lds<T>::type *vp, typename Lds<T>::type *vq, int N, T tol,
+                                                T atol) {
+    const int lane = threadIdx.x & 63;
+    T al = 0, be = 0, ga = 0;
+    for (int i = lane; i < N; i += 64) {
+        const T a = gp[i], b = gq[i];
+        al += a * a;
+        be += b * b;
+        ga += a * b;
+    }
+    al = wave_allsum(al);
+    be = wave_allsum(be);
+    ga = wave_allsum(ga);
+    T c, s;
+    if (!jacobi_rot<T>(al, be, ga, tol * tol, atol * atol, c, s)) return 0;
+    for (int i = lane; i < N; i += 64) {
+        const T a = gp[i], b = gq[i];
+        gp[i] = c * a - s * b;
+        gq[i] = s * a + c * b;
+        const T x = vp[i], y = vq[i];
+        vp[i] = c * x - s * y;
+        vq[i] = s * x + c * y;
+    }
+    return ga * ga > tol * (al * be) ? 2 : 1;
+}
+
+// P_{S+} of one block over the whole grid: G, V, W (N x N, column-major, ld N) and sigma (N) in
+// global scratch.  Block one-sided Jacobi: the columns form blocks of bcols; in each block round
+// (round-robin over the blocks, as the scalar form pairs columns) a workgroup takes a pair of
+// blocks into LDS and applies one cyclic sweep over all pairs of their 2 bcols columns, one
+// wavefront per column pair; a grid barrier ends the round.  Every pair of columns meets once per
+// sweep of block rounds; sweeps stop as in the single-workgroup forms (a sweep whose rotations all
+// had relative coupling at most sqrt(tol)), the vote collected in global memory.  Every workgroup
+// passes the same barriers: the same block rounds per sweep, and the same vote after the last.
+template <typename T, int NT>
+__device__ __noinline__ void coop_project_block(T *__restrict__ vs, T *__restrict__ us, int N, T *__restrict__ Vs,
+                                                bool warm, T *__restrict__ G, T *__restrict__ V, T *__restrict__ W,
+                                                T *__restrict__ sig, double *parts, CoopCtl *ctl, int bcols,
+                                                int max_sweeps, double jtol, char *dyn_lds, double *s_red,
+                                                double *s_red1, int *nsweeps, int &gsw) {
+    typedef typename Lds<T>::type LT;
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wg = blockIdx.x, nwg = gridDim.x;
+    const long long gt = (long long)wg * NT + tid, gstride = (long long)nwg * NT;
+    const int w0 = wg * NW + wid, nw = nwg * NW;
+    // stage: G = W and V = I (cold), or W and V = V_prev (warm); |W|_F^2 from the packed triangle
+    double fro2 = 0.0;
+    for (long long idx = gt; idx < (long long)N * N; idx += gstride) {
+        const int j = (int)(idx / N), i = (int)(idx - (long long)j * N);
+        const int a = i > j ? i : j, b = i > j ? j : i;
+        const T x = vs[svec_idx(a, b, N)];
+        if (warm) {
+            W[idx] = x;
+            V[idx] = Vs[idx];
+        } else {
+            G[idx] = x;
+            V[idx] = (i == j) ? (T)1 : (T)0;
+        }
+        fro2 += (double)x * (double)x;
+    }
+    {
+        double d = 0.0;
+        block_sum2<NT>(fro2, d, s_red);   // every thread: this workgroup's part
+    }
+    fro2 = grid_sum(fro2, parts, ctl, s_red1);   // its barriers also publish G, V, W
+    if (warm) {
+        mfma_wv<T, NT>(W, N, true, V, N, G, N, N, false, w0, nw);
+        grid_sync(ctl);
+    }
+    const T tol = jacobi_tol<T>(jtol);
+    const T atol = (T)(jacobi_atol_factor(N) * TS<T>::eps * sqrt(fro2));
+    const int nb = (N + bcols - 1) / bcols, nbp = nb + (nb & 1);
+    LT *lg = as_lds<T>(dyn_lds);                      // [2 bcols][N]
+    LT *lv = lg + (long long)2 * bcols * N;           // [2 bcols][N]
+    __shared__ int s_big;
+    int sweep = 0;
+    while (sweep < max_sweeps) {
+        // vote flags by the launch's running sweep count gsw (a projection's first sweep continues
+        // where the last one stopped, so no flag is read before it was reset for its sweep)
+        const int fl = gsw % 3;
+        if (wg == 0 && tid == 0) __hip_atomic_store(&ctl->big[(gsw + 1) % 3], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) s_big = 0;
+        __syncthreads();
+        for (int R = 0; R < nbp - 1; ++R) {
+            for (int pk = wg; pk < nbp / 2; pk += nwg) {
+                int P0, Q0;
+                rr_pair(R, pk, nbp, P0, Q0);
+                const int p0 = P0 * bcols, p1 = min(N, p0 + bcols);
+                const int q0 = Q0 < nb ? Q0 * bcols : 0, q1 = Q0 < nb ? min(N, q0 + bcols) : 0;
+                const int np = p1 - p0, c = np + (q1 - q0);
+                // local column lc: global column p0 + lc (lc < np) or q0 + lc - np
+                for (int idx = tid; idx < c * N; idx += NT) {
+                    const int lc = idx / N, i = idx - lc * N;
+                    const int col = lc < np ? p0 + lc : q0 + lc - np;
+                    lg[idx] = G[(long long)col * N + i];
+                    lv[idx] = V[(long long)col * N + i];
+                }
+                __syncthreads();
+                const int M2 = c + (c & 1);
+                int big = 0;
+                for (int r = 0; r < M2 - 1; ++r) {
+                    for (int kk = wid; kk < M2 / 2; kk += NW) {
+                        int p, q;
+                        rr_pair(r, kk, M2, p, q);
+                        if (q < c && wave_rotate_pair<T>(lg + (long long)p * N, lg + (long long)q * N, lv + (long long)p * N,
+                                                         lv + (long long)q * N, N, tol, atol) == 2)
+                            big = 1;
+                    }
+                    __syncthreads();
+                }
+                if (big && lane == 0) s_big = 1;
+                for (int idx = tid; idx < c * N; idx += NT) {
+                    const int lc = idx / N, i = idx - lc * N;
+                    const int col = lc < np ? p0 + lc : q0 + lc - np;
+                    G[(long long)col * N + i] = lg[idx];
+                    V[(long long)col * N + i] = lv[idx];
+                }
+                __syncthreads();
+            }
+            if (R == nbp - 2 && tid == 0 && s_big)
+                __hip_atomic_store(&ctl->big[fl], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            grid_sync(ctl);
+        }
+        const int any = __hip_atomic_load(&ctl->big[fl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ++sweep;
+        ++gsw;
+        if (!any) break;
+    }
+    if (wg == 0 && tid == 0) *nsweeps += sweep;
+    // sigma_j = |g_j|, one wavefront per column
+    for (int j = w0; j < N; j += nw) {
+        T sacc = 0;
+        for (int i = lane; i < N; i += 64) sacc += G[(long long)j * N + i] * G[(long long)j * N + i];
+        sacc = wave_allsum(sacc);
+        if (lane == 0) sig[j] = sqrt(sacc);
+    }
+    grid_sync(ctl);
+    mfma_rebuild<T, NT>(V, N, sig, N, vs, us, w0, nw);
+    if (Vs)
+        for (long long idx = gt; idx < (long long)N * N; idx += gstride) Vs[idx] = V[idx];
+    grid_sync(ctl);
+}
+
+// Whole FP64 iterations of one problem over a cooperative grid (see sos_launch_admm_coop).
+template <int NT>
+__global__ __launch_bounds__(NT) void admm_coop(RunParams rp, CoopCtl *ctl, double *scr, int bcols) {
+    typedef double T;
+    __shared__ double s_red[4 * (NT / 64)];
+    __shared__ double s_red1;
+    __shared__ int s_sweeps;
+    extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+    const ProbDesc &P = rp.probs[0];
+    const int wg = blockIdx.x, tid = threadIdx.x;
+    const int nm = P.nmax;
+    T *G = scr, *V = G + (long long)nm * nm, *W = V + (long long)nm * nm, *sig = W + (long long)nm * nm;
+    double *parts = sig + nm;
+    T *wy = reinterpret_cast<T *>(rp.work);
+    T *wx = wy + ((P.m + 63) & ~63);
+    double *s_z = reinterpret_cast<double *>(dyn_lds);
+    T *u = P.u64, *v = P.v64, *vstore = P.vs64;
+    bool warm = P.tk[2] != 0.0;
+    if (tid == 0) s_sweeps = 0;
+    int it = 0, status = 0, gsw = 0;
+    unsigned long long t_aff = 0, t_eig = 0, t_res = 0;
+    const int cap = rp.iters;
+    while (it < cap) {
+        const unsigned long long t0 = wall_clock64();
+        if (wg == 0) affine_phase<T, NT, T>(P, rp, wy, wx, s_z, s_red);
+        grid_sync(ctl);
+        const unsigned long long t1 = wall_clock64();
+        t_aff += t1 - t0;
+        long long voff = 0;
+        for (int bk = 0; bk < P.nblk; ++bk) {
+            const int off = P.blk_off[bk], N = P.blk_N[bk];
+            coop_project_block<T, NT>(v + off, u + off, N, rp.warm_eig ? vstore + voff : nullptr, rp.warm_eig && warm, G, V,
+                                      W, sig, parts, ctl, bcols, rp.max_sweeps, rp.jacobi_tol, dyn_lds, s_red, &s_red1,
+                                      &s_sweeps, gsw);
+            voff += (long long)N * N;
+        }
+        warm = rp.warm_eig != 0;
+        ++it;
+        const unsigned long long t2 = wall_clock64();
+        t_eig += t2 - t1;
+        if (rp.mode == RUN_SOLVE && (it % rp.check_every == 0 || it == cap)) {
+            if (wg == 0) {
+                const int st = residual_phase<T, NT>(P, rp.tol, s_red, it);
+                if (tid == 0) __hip_atomic_store(&ctl->status, st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            grid_sync(ctl);
+            status = __hip_atomic_load(&ctl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            t_res += wall_clock64() - t2;
+            if (status) break;
+        }
+    }
+    if (wg == 0) {
+        if (rp.mode == RUN_STEP || status == 0) {
+            status = residual_phase<T, NT>(P, rp.tol, s_red, it);
+            if (rp.mode == RUN_SOLVE && status == 0 && tid == 0) P.out[SOS_OUT_STATUS] = 4;
+        }
+        if (tid == 0) {
+            P.out[SOS_OUT_T_AFFINE] = (double)t_aff;
+            P.out[SOS_OUT_T_EIG] = (double)t_eig;
+            P.out[SOS_OUT_T_RES] = (double)t_res;
+            P.out[SOS_OUT_SWEEPS] = (it > 0 && P.nblk > 0) ? (double)s_sweeps / ((double)it * P.nblk) : 0.0;
+            P.out[SOS_OUT_TOTAL] = it;
+            P.out[SOS_OUT_WARM] = 0;
+            if (it > 0) P.tk[2] = rp.warm_eig ? 1.0 : 0.0;
+            if (rp.mode == RUN_SOLVE) P.tk[3] = 0.0;
+        }
+    }
+}
+
+__global__ void reset_coop(CoopCtl *ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl->count = 0;
+        ctl->gen = 0;
+        ctl->err = 0;
+        ctl->status = 0;
+        ctl->big[0] = ctl->big[1] = ctl->big[2] = 0;
+    }
+}
+
 // Learned warm start: from a predicted (xi, y) (FP32 rows, internal layout), set
 //   u = (P_K(xi), y, 1),  v = (P_{K*}(c - A^T y), 0, 0)
 // for every problem of a batch.  Launched on the batch's persistent grid (whose
@@ -1874,6 +2154,67 @@ int sos_static_scratch(void **ptr) {
         addr[dev] = p;
     }
     *ptr = addr[dev];
+    return 0;
+}
+
+// dynamic LDS of a cooperative launch: the affine step's k-vector and partial sums, or the
+// Jacobi blocks' columns of G and V (the two phases are separated by barriers)
+static size_t coop_lds_bytes(const RunParams &rp, int bcols) {
+    const size_t jac = sizeof(double) * 4 * (size_t)bcols * rp.eig_ld;
+    const size_t aff = sizeof(double) * 2 * SOS_KMAX_LDS;
+    return jac > aff ? jac : aff;
+}
+
+int sos_coop_max_grid(int threads, const RunParams &rp, int bcols) {
+    const size_t lds = coop_lds_bytes(rp, bcols);
+    if (lds > (size_t)rp.lds_budget) return 0;
+    int dev = 0, coop = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const void *f = nullptr;
+    switch (threads) {
+        case 256: f = reinterpret_cast<const void *>(&admm_coop<256>); break;
+        case 512: f = reinterpret_cast<const void *>(&admm_coop<512>); break;
+        default: return 0;
+    }
+    if (lds > 64 * 1024) {
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, threads, lds) != hipSuccess || per < 1) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const int g = cus * per;
+    return g < SOS_COOP_MAX_WG ? g : SOS_COOP_MAX_WG;
+}
+
+int sos_launch_admm_coop(int threads, int grid, const RunParams &rp_in, CoopCtl *ctl, double *scratch, int bcols,
+                         void *stream) {
+    RunParams rp = rp_in;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (grid < 1 || grid > SOS_COOP_MAX_WG || bcols < 1) return -1;
+    const size_t lds = coop_lds_bytes(rp, bcols);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(reset_coop, dim3(1), dim3(64), 0, st, ctl);
+    void *args[] = {&rp, &ctl, &scratch, &bcols};
+    hipError_t e;
+    switch (threads) {
+        case 256:
+            e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&admm_coop<256>), dim3(grid), dim3(256), args,
+                                           (unsigned)lds, st);
+            break;
+        case 512:
+            e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&admm_coop<512>), dim3(grid), dim3(512), args,
+                                           (unsigned)lds, st);
+            break;
+        default: return -1;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return -4;
+    }
     return 0;
 }
 

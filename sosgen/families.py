@@ -256,6 +256,20 @@ def univariate(coeffs_low_to_high: Sequence[float]) -> ConicProblem:
     return pop_from_poly(p, deg // 2, {"family": "univariate"})
 
 
+def univariate_stack(polys: Sequence[Sequence[float]]) -> ConicProblem:
+    """max sum_i gamma_i s.t. p_i - gamma_i SOS for several univariate polynomials at once: one
+    SOS equation, free variable and Gram block per polynomial (a program with as many PSD blocks
+    as polynomials); the optimum is gamma_i = min p_i for each."""
+    eqs = []
+    for i, a in enumerate(polys):
+        deg = len(a) - 1
+        if deg % 2:
+            raise ValueError("even degrees only")
+        p = Poly(1, {(k,): float(c) for k, c in enumerate(a) if c != 0.0})
+        eqs.append(SOSEquation(row_degree=deg, g0=p, g={i: Poly.const(1, 1.0)}, blocks=[(deg // 2, Poly.const(1, 1.0))]))
+    return build_sos_sdp(1, len(polys), [-1.0] * len(polys), eqs, {"kind": "univariate_stack", "count": len(polys)})
+
+
 def bivariate_quartic(seed: int) -> ConicProblem:
     """x^4 + y^4 + N(0,1) on every monomial of degree <= 3 in two variables."""
     rng = np.random.default_rng(seed)

@@ -14,6 +14,9 @@ comes from the GPU library.  Entries:
   gamma error), and the status at tol 1e-4 / 2000 iterations.
 * pop_n20: status and iterations of the unconstrained quartic POP n = 20 with N(0, 0.1) quartic
   cross terms (Gram block 231, m = 10626), seed 0, tol 1e-4, 2000 iterations.
+* example_pop_n24: the test POP of Section VII-A at n = 24 (blocks 325 and 25, m = 20475; Table
+  I's n = 24 row), status, iterations and gamma at tol 1e-4 / 2000 iterations, and gamma at tol 1e-7
+  (compared with the brute-force minimum by a CPU test).
 
 Usage: python tests/golden/make_oracle_tables.py [--only KEY ...] [--workers N]
 """
@@ -39,7 +42,8 @@ def _solve(args):
     from oracle.admm import Oracle
     from sosgen import families as F
     make = {"lyapunov": F.lyapunov, "ball16": lambda s: F.pop_ball(16, s),
-            "pop20": lambda s: F.pop_unconstrained(20, s, cross_std=0.1)}[kind]
+            "pop20": lambda s: F.pop_unconstrained(20, s, cross_std=0.1),
+            "example": lambda s: F.example_pop(s)}[kind]
     t = time.perf_counter()
     with threadpool_limits(limits=1):
         r = Oracle.from_problem(make(seed)).solve(tol=tol, max_iters=max_iters, check_every=10)
@@ -57,15 +61,17 @@ def main():
     args = ap.parse_args()
     table = json.load(open(OUT)) if os.path.exists(OUT) else {}
     jobs = []
-    want = set(args.only) if args.only else {"lyapunov_512", "ball_pop_n16", "pop_n20"}
+    want = set(args.only) if args.only else {"lyapunov_512", "ball_pop_n16", "pop_n20", "example_pop_n24"}
     if "lyapunov_512" in want:
         jobs += [("lyapunov", s, 1e-4, 2000) for s in range(3584, 4096)]
     if "ball_pop_n16" in want:
         jobs += [("ball16", s, 1e-7, 50000) for s in range(3)] + [("ball16", s, 1e-4, 2000) for s in range(3)]
     if "pop_n20" in want:
         jobs += [("pop20", 0, 1e-4, 2000)]
+    if "example_pop_n24" in want:
+        jobs += [("example", 24, 1e-4, 2000), ("example", 24, 1e-7, 20000)]
     # slowest first, so the pool's tail is short
-    jobs.sort(key=lambda j: {"ball16": 0, "pop20": 1, "lyapunov": 2}[j[0]])
+    jobs.sort(key=lambda j: {"example": 0, "ball16": 0, "pop20": 1, "lyapunov": 2}[j[0]])
     res = {}
     with ProcessPoolExecutor(max_workers=args.workers) as ex:
         for kind, seed, tol, out in ex.map(_solve, jobs):
@@ -84,6 +90,9 @@ def main():
     if "pop_n20" in want:
         table["pop_n20"] = dict(common, tol=1e-4, max_iters=2000, cross_std=0.1,
                                 seeds={"0": res[("pop20", 0, 1e-4)]})
+    if "example_pop_n24" in want:
+        table["example_pop_n24"] = dict(common, n=24, tol=1e-4, max_iters=2000, result=res[("example", 24, 1e-4)],
+                                        tight=dict(tol=1e-7, max_iters=20000, result=res[("example", 24, 1e-7)]))
     with open(OUT, "w") as f:
         json.dump(table, f, indent=1, sort_keys=True)
     print("wrote", OUT)

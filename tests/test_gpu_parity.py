@@ -283,7 +283,7 @@ def test_setup_errors(B):
 def test_settings_and_schedule_errors(B):
     prob = F.FAMILIES["c1"](0)
     with pytest.raises(B.SosError) as e:
-        B.setup_problem(prob, B.sos_default_settings(eig_form=3))
+        B.setup_problem(prob, B.sos_default_settings(eig_form=4))
     assert e.value.code == B.SOS_E_INVAL
     works = [B.setup_problem(F.pop_unconstrained(4, sd)) for sd in (0, 1)]
     for bad in ('{"eig_wave": 1}', '{"rows_nmin": -1}', '{"stall_checks": 0}', '{"fp64_jacobi_tol": 0.01}',
@@ -450,3 +450,79 @@ def test_mixed_one_launch_equals_two_launches(B):
     assert res[0][0] == res[1][0]
     for (u1, v1), (u2, v2) in zip(res[0][1], res[1][1]):
         assert np.array_equal(u1, u2) and np.array_equal(v1, v2)
+
+
+# ---------------------------------------------------------------- multi-workgroup (cooperative) form
+COOP_CASES = {
+    "c1_seed0": lambda: F.FAMILIES["c1"](0),                 # one block of 15: a single column block pair
+    "lyapunov_c5_seed0": lambda: F.FAMILIES["c5"](0),        # blocks 84 and 28, k = 203
+    "ball_n3_weighted": lambda: F.pop_ball(3, 2),             # blocks 10 and 4
+    "pop_n14": lambda: F.pop_unconstrained(14, 0),            # block 120: 15 column blocks (odd)
+}
+
+
+@pytest.mark.parametrize("name", list(COOP_CASES))
+def test_step_parity_multi_workgroup(B, name):
+    # eig_form 3: every block through the cooperative grid (block Jacobi, grid barriers)
+    s = B.sos_default_settings(eig_form=3)
+    _step_parity(B, COOP_CASES[name](), [1, 3, 12], settings=s, tag=f"{name}_coop")
+
+
+def test_solve_parity_multi_workgroup(B):
+    for seed in (0, 1):
+        prob = F.FAMILIES["c1"](seed)
+        r = Oracle.from_problem(prob).solve(tol=1e-6, max_iters=5000)
+        w = B.setup_problem(prob, B.sos_default_settings(tol=1e-6, max_iters=5000, eig_form=3))
+        inf = B.sos_solve(w)
+        x, _, _ = B.sos_get_solution(w)
+        w.free()
+        print(f"[parity] coop c1 seed {seed}: gpu {inf['status_name']} {inf['iters']} gamma {x[0]:.9f}; "
+              f"oracle {r.status_name} {r.iters} gamma {r.x[0]:.9f}", flush=True)
+        assert inf["status"] == r.status == 1 and inf["iters"] == r.iters
+        assert abs(x[0] - r.x[0]) <= 1e-6 * max(1.0, abs(r.x[0]))
+
+
+def test_example_pop_n24_through_sos_solve(B):
+    # the paper's test POP (Section VII-A) at n = 24: blocks 325 and 25, m = 20475 (Table I's
+    # n = 24 row); FP64 on the multi-workgroup form, against the oracle's stored solve
+    ref = TABLES["example_pop_n24"]
+    prob = F.example_pop(24)
+    assert prob.psd_dims == [325, 25] and prob.m == 20475
+    w = B.setup_problem(prob, B.sos_default_settings(tol=ref["tol"], max_iters=ref["max_iters"]))
+    inf = B.sos_solve(w)
+    x, _, _ = B.sos_get_solution(w)
+    w.free()
+    o = ref["result"]
+    print(f"[parity] example POP n = 24: gpu {inf['status_name']} {inf['iters']} gamma {x[0]:.9f} "
+          f"({inf['solve_ms'] / max(inf['iters'], 1):.2f} ms/iter, {inf['eig_sweeps']:.1f} sweeps); "
+          f"oracle {o['status']} {o['iters']} gamma {o['gamma']:.9f}", flush=True)
+    assert inf["status"] == o["status"] == 1 and inf["iters"] == o["iters"]
+    assert abs(x[0] - o["gamma"]) <= 1e-6 * abs(o["gamma"])
+
+
+@pytest.mark.parametrize("form", [0, 2])
+def test_step_parity_wide_lowrank_part(B, form):
+    # ball POP n = 8 at 2d = 6: Gram blocks 165 and 45, the weighted block's 1035 lower-triangle
+    # columns in A_f (k = 1036, past the LDS k-vector); the multi-workgroup and one-workgroup forms
+    prob = F.pop_ball(8, 0, form="weighted", half_degree=3)
+    assert prob.psd_dims == [165, 45]
+    s = B.sos_default_settings(eig_form=form)
+    w = B.setup_problem(prob, s)
+    assert B.sos_step(w, 0)["k_lowrank"] == 1036
+    w.free()
+    _step_parity(B, prob, [1, 3], settings=s, tag=f"ball_n8_2d6_form{form}")
+
+
+def test_many_blocks_step_and_solve(B):
+    # ten Gram blocks in one program (past the former limit of eight)
+    rng = np.random.default_rng(400)
+    polys = [np.concatenate([rng.standard_normal(4), [1.0]]) for _ in range(10)]
+    prob = F.univariate_stack(polys)
+    _step_parity(B, prob, [1, 5, 40], tag="univariate_stack_10")
+    r = Oracle.from_problem(prob).solve(tol=1e-6, max_iters=20000)
+    w = B.setup_problem(prob, B.sos_default_settings(tol=1e-6, max_iters=20000))
+    inf = B.sos_solve(w)
+    x, _, _ = B.sos_get_solution(w)
+    w.free()
+    assert inf["status"] == r.status == 1 and inf["iters"] == r.iters
+    assert np.max(np.abs(x[:10] - r.x[:10])) <= 1e-6 * max(1.0, np.max(np.abs(r.x[:10])))

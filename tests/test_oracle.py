@@ -283,3 +283,32 @@ def test_planted_projection_mistake_is_caught():
     except (ValueError, np.linalg.LinAlgError):
         caught = True                      # the iteration diverged to non-finite values
     assert caught
+
+
+def test_example_pop_n24_stored_oracle_value_matches_brute_force():
+    # Table I's n = 24 row (blocks 325 and 25, m = 20475): the stored oracle value (written by
+    # tests/golden/make_oracle_tables.py, tol 1e-7) against the brute-force minimum on the ball
+    tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_tables.json")))
+    ent = tab["example_pop_n24"]
+    gamma = ent["tight"]["result"]["gamma"]
+    n = 24
+    starts = [s * np.eye(n)[k] for k in range(n) for s in (1, -1)]
+    ref = _global_min(F.example_pop_poly(n), n, True, starts)
+    assert gamma <= ref + 1e-5 and abs(gamma - ref) <= 2e-5 * abs(ref), (gamma, ref)
+    assert gamma <= -(n - 1)
+    assert abs(ent["result"]["gamma"] - gamma) <= 1e-4 * abs(gamma)     # the tol 1e-4 solve is close
+
+
+def test_stack_of_univariate_pops_with_many_blocks():
+    # ten univariate POPs in one program (ten Gram blocks): gamma_i = min p_i by brute force
+    rng = np.random.default_rng(400)
+    polys = [np.concatenate([rng.standard_normal(4), [1.0]]) for _ in range(10)]
+    prob = F.univariate_stack(polys)
+    assert len(prob.psd_dims) == 10 and prob.n_free == 10
+    r = Oracle.from_problem(prob).solve(tol=1e-8, max_iters=50000)
+    assert r.status == SOLVED
+    for i, a in enumerate(polys):
+        crit = np.roots(np.polyder(a[::-1]))
+        crit = crit[np.abs(crit.imag) < 1e-9].real
+        pmin = min(np.polyval(a[::-1], crit))
+        assert abs(r.x[i] - pmin) <= 1e-5 * max(1.0, abs(pmin)), (i, r.x[i], pmin)

@@ -63,8 +63,9 @@ def test_static_scratch_matches_sos_step_on_two_calls(B, precision):
 
 def test_static_scratch_on_a_large_block_then_a_small_one(B):
     # a 153 x 153 block (quartic POP, n = 16; global-memory eigensolver scratch in FP64), then
-    # the 15 x 15 one again
-    s = B.sos_default_settings()
+    # the 15 x 15 one again; eig_form 2 keeps sos_step on one workgroup too (by default a block
+    # this large takes the multi-workgroup form there, which the static entry point does not run)
+    s = B.sos_default_settings(eig_form=2)
     _same("fp64 pop n=16 (153)", *_pair(B, F.pop_unconstrained(16, 0), s, 3))
     _same("fp64 pop n=4 (15) after", *_pair(B, F.FAMILIES["c1"](1), s, 10))
 
