@@ -326,21 +326,19 @@ def main():
             infos, sol, tb = W.cold_solve_batch(tw, sched)
             keep = [j for j, inf in enumerate(infos) if inf["status"] == B.SOS_SOLVED]
             X.append(WL.lyapunov_features([train_seeds[i + j] for j in keep]))
-            T.append(sol[torch.tensor(keep, device="cuda")].contiguous())
+            T.append(sol.cpu().numpy()[keep])   # host copy: row selection is data preparation
             nsolved = nsolved + len(keep)
             tb.free()
             for w in tw:
                 w.free()
             log(f"[bench] training data {i + len(chunk)}/{len(train_probs)}: {len(keep)} solved")
-        Xtr = torch.from_numpy(np.concatenate(X)).cuda()
-        Ttr = torch.cat(T).contiguous()
-        mask = W.training_mask(Ttr)
-        Xtr, Ttr = Xtr[mask].contiguous(), Ttr[mask].contiguous()
-        log(f"[bench] training set: {int(mask.sum())} of {nsolved} solved instances (norm <= 3 x median)")
+        Xtr, Ttr = np.concatenate(X), np.concatenate(T)
+        rows = np.nonzero(W.training_mask(Ttr))[0]
+        log(f"[bench] training set: {len(rows)} of {nsolved} solved instances (norm <= 3 x median)")
         t1 = time.perf_counter()
         model = W.WarmStartModel(Xtr.shape[1], Ttr.shape[1], hidden=512, max_batch=4096, seed=0)
-        losses = model.fit(Xtr, Ttr, epochs=args.epochs, batch=256, lr=1e-3, log=log)
-        train_info = {"instances": int(Xtr.shape[0]), "epochs": args.epochs, "final_loss": losses[-1],
+        losses = model.fit(Xtr, Ttr, rows=rows, epochs=args.epochs, batch=256, lr=1e-3, log=log)
+        train_info = {"instances": int(len(rows)), "epochs": args.epochs, "final_loss": losses[-1],
                       "data_s": t1 - t0, "fit_s": time.perf_counter() - t1}
         log(f"[bench] model: {train_info}")
         Xte = torch.from_numpy(WL.lyapunov_features(test_seeds)).cuda()

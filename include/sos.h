@@ -255,6 +255,10 @@ double sos_batch_last_ms(const sos_batch *b);
    two-launch mixed form (0 otherwise).  Returns a negative value if unavailable. */
 double sos_batch_phase_ms(const sos_batch *b, int32_t phase);
 
+/* Message for the last failed call on batch b (NULL: the last failed sos_batch_setup, as
+   sos_last_error(NULL) gives it). */
+const char *sos_batch_last_error(const sos_batch *b);
+
 void sos_batch_free(sos_batch *b);
 
 /* ---------------------------------------------------------------- learned warm start
@@ -295,6 +299,12 @@ int sos_mlp_gradient(sos_mlp *m, const float *X_dev, const float *T_dev, int32_t
                      double *loss_host);
 /* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on mean((Y - T)^2); loss_host may be NULL */
 int sos_mlp_train_step(sos_mlp *m, const float *X_dev, const float *T_dev, int32_t batch, float lr, double *loss_host);
+/* sos_mlp_train_step on a mini-batch given by row indices: rows rows_dev[0..batch) of X_dev (n_in
+   columns) and T_dev (n_out columns), both row-major FP32 device arrays, are gathered by a device
+   kernel into the MLP's own batch buffers, so a caller shuffles by index only.  rows_dev: device
+   int32 array; every index must lie inside X_dev and T_dev (not checked on the device). */
+int sos_mlp_train_step_rows(sos_mlp *m, const float *X_dev, const float *T_dev, const int32_t *rows_dev, int32_t batch,
+                            float lr, double *loss_host);
 void sos_mlp_free(sos_mlp *m);
 
 #ifdef __cplusplus

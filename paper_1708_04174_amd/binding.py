@@ -24,11 +24,11 @@ STATUS_NAMES = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_inf
 
 EXPORTED = ["sos_default_settings", "sos_setup", "sos_step", "sos_step_static", "sos_solve", "sos_warm_start",
             "sos_get_solution", "sos_get_iterate", "sos_set_iterate", "sos_psd_factor", "sos_last_error", "sos_free",
-            "sos_batch_setup", "sos_batch_solve", "sos_batch_reset", "sos_batch_last_ms",
+            "sos_batch_setup", "sos_batch_solve", "sos_batch_reset", "sos_batch_last_ms", "sos_batch_last_error",
             "sos_batch_phase_ms", "sos_batch_free", "sos_layout_size", "sos_batch_warm_start",
             "sos_batch_export_solutions", "sos_mlp_create", "sos_mlp_num_params", "sos_mlp_set_params",
             "sos_mlp_get_params", "sos_mlp_set_output_affine", "sos_mlp_forward", "sos_mlp_gradient",
-            "sos_mlp_train_step", "sos_mlp_free"]
+            "sos_mlp_train_step", "sos_mlp_train_step_rows", "sos_mlp_free"]
 
 
 class SosError(RuntimeError):
@@ -108,6 +108,8 @@ def load():
     lib.sos_batch_phase_ms.argtypes = [vp, C.c_int32]
     lib.sos_batch_phase_ms.restype = C.c_double
     lib.sos_batch_free.argtypes = [vp]
+    lib.sos_batch_last_error.argtypes = [vp]
+    lib.sos_batch_last_error.restype = C.c_char_p
     lib.sos_batch_free.restype = None
     fp = P(C.c_float)
     lib.sos_layout_size.argtypes = [vp]
@@ -123,10 +125,12 @@ def load():
     lib.sos_mlp_forward.argtypes = [vp, vp, C.c_int32, vp, C.c_int32]
     lib.sos_mlp_gradient.argtypes = [vp, vp, vp, C.c_int32, fp, P(C.c_double)]
     lib.sos_mlp_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, P(C.c_double)]
+    lib.sos_mlp_train_step_rows.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, P(C.c_double)]
     lib.sos_mlp_free.argtypes = [vp]
     lib.sos_mlp_free.restype = None
     for name in EXPORTED:
-        if name not in ("sos_free", "sos_batch_free", "sos_last_error", "sos_batch_last_ms", "sos_batch_phase_ms",
+        if name not in ("sos_free", "sos_batch_free", "sos_last_error", "sos_batch_last_error", "sos_batch_last_ms",
+                        "sos_batch_phase_ms",
                         "sos_layout_size", "sos_mlp_num_params", "sos_mlp_free"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -137,9 +141,9 @@ def _dptr(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def _check(rc: int, handle=None):
+def _check(rc: int, handle=None, batch=None):
     if rc != SOS_OK:
-        msg = load().sos_last_error(handle)
+        msg = load().sos_batch_last_error(batch) if batch is not None else load().sos_last_error(handle)
         raise SosError(rc, msg.decode() if msg else "")
 
 
@@ -302,12 +306,12 @@ def sos_batch_setup(works: Sequence[Work], schedule_json: Optional[str] = None) 
 
 def sos_batch_solve(batch: Batch) -> List[dict]:
     infos = (sos_info * len(batch.works))()
-    _check(load().sos_batch_solve(batch.handle, infos), None)
+    _check(load().sos_batch_solve(batch.handle, infos), batch=batch.handle)
     return [i.as_dict() for i in infos]
 
 
 def sos_batch_reset(batch: Batch) -> None:
-    _check(load().sos_batch_reset(batch.handle), None)
+    _check(load().sos_batch_reset(batch.handle), batch=batch.handle)
 
 
 def sos_batch_last_ms(batch: Batch) -> float:
@@ -342,12 +346,12 @@ def _check_rows(t, count: int, ld: int):
 def sos_batch_warm_start(batch: Batch, pred, ld: int) -> None:
     """pred: cuda float32 tensor with one row of ld >= nx + m values per problem."""
     _check_rows(pred, len(batch.works), ld)
-    _check(load().sos_batch_warm_start(batch.handle, _dev(pred), int(ld)), None)
+    _check(load().sos_batch_warm_start(batch.handle, _dev(pred), int(ld)), batch=batch.handle)
 
 
 def sos_batch_export_solutions(batch: Batch, out, ld: int) -> None:
     _check_rows(out, len(batch.works), ld)
-    _check(load().sos_batch_export_solutions(batch.handle, _dev(out), int(ld)), None)
+    _check(load().sos_batch_export_solutions(batch.handle, _dev(out), int(ld)), batch=batch.handle)
 
 
 class MLP:
@@ -397,6 +401,18 @@ class MLP:
         _check(load().sos_mlp_gradient(self.handle, _dev(X), _dev(T), X.shape[0],
                                        g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss)), None)
         return g, loss.value
+
+    def train_step_rows(self, X, T, rows, lr: float, want_loss: bool = False):
+        """One Adam step on rows `rows` (a contiguous int32 cuda tensor) of X and T, gathered by the
+        library."""
+        import torch
+        assert rows.is_cuda and rows.dtype == torch.int32 and rows.is_contiguous()
+        assert X.shape[1] == self.n_in and T.shape[1] == self.n_out
+        loss = C.c_double()
+        _check(load().sos_mlp_train_step_rows(self.handle, _dev(X), _dev(T), C.c_void_p(rows.data_ptr()),
+                                              int(rows.shape[0]), float(lr), C.byref(loss) if want_loss else None),
+               None)
+        return loss.value if want_loss else None
 
     def train_step(self, X, T, lr: float, want_loss: bool = False):
         loss = C.c_double()

@@ -152,6 +152,7 @@ struct sos_batch {
     bool used_one_launch = false;
     int gs_bucket[7] = {16, 16, 16, 16, 16, 16, 16};
     sos_settings st{};
+    std::string err;   // message of the last failed call on the batch
 };
 
 namespace {
@@ -648,7 +649,7 @@ void setup_coop(sos_work *w) {
 // the FP64 iterations of a single solve over the cooperative grid; checks the barrier's flag
 void run_coop(sos_work *w, const RunParams &rp) {
     if (sos_launch_admm_coop(w->coop_threads, w->coop_grid, rp, w->d_ctl, w->d_coop_scr, w->coop_bcols, w->stream))
-        throw Status(SOS_E_HIP, "cooperative launch failed");
+        throw Status(SOS_E_HIP, std::string("cooperative launch failed: ") + sos_launch_message());
     CoopCtl c;
     hip_check(hipMemcpyAsync(&c, w->d_ctl, sizeof(c), hipMemcpyDeviceToHost, w->stream), "copy");
     hip_check(hipStreamSynchronize(w->stream), "sync");
@@ -682,14 +683,14 @@ RunParams single_params(sos_work *w, int mode, int iters, int min_iters, double 
 }
 
 void run_single(sos_work *w, int fp64, const RunParams &rp) {
-    if (sos_launch_reset(rp.counter, w->stream)) throw Status(SOS_E_HIP, "reset launch failed");
-    if (sos_launch_admm(fp64, w->threads, 1, rp, w->stream)) throw Status(SOS_E_HIP, "solver launch failed");
+    if (sos_launch_reset(rp.counter, w->stream)) throw Status(SOS_E_HIP, std::string("reset launch failed: ") + sos_launch_message());
+    if (sos_launch_admm(fp64, w->threads, 1, rp, w->stream)) throw Status(SOS_E_HIP, std::string("solver launch failed: ") + sos_launch_message());
 }
 
 void set_active(sos_work *w, bool to64) {
     if (w->active64 == to64) return;
     if (sos_launch_cast_state(w->d_desc, nullptr, 1, to64 ? 1 : 0, w->stream, w->nx + w->m))
-        throw Status(SOS_E_HIP, "cast launch failed");
+        throw Status(SOS_E_HIP, std::string("cast launch failed: ") + sos_launch_message());
     w->active64 = to64;
 }
 
@@ -749,7 +750,7 @@ void step_impl(sos_work *w, int32_t iters, sos_info *info, bool static_scratch) 
     hip_check(hipEventRecord(w->ev0, w->stream), "event");
     if (fp64 && w->use_coop && !static_scratch) {
         if (sos_launch_admm_coop(w->coop_threads, w->coop_grid, rp, w->d_ctl, w->d_coop_scr, w->coop_bcols, w->stream))
-            throw Status(SOS_E_HIP, "cooperative launch failed");
+            throw Status(SOS_E_HIP, std::string("cooperative launch failed: ") + sos_launch_message());
     } else {
         run_single(w, fp64, rp);
     }
@@ -778,6 +779,24 @@ int guarded(sos_work *w, F &&f) {
         return s.code;
     } catch (const std::bad_alloc &) {
         if (w) w->err = "host allocation failed";
+        return SOS_E_NOMEM;
+    }
+}
+
+// as guarded, with the message kept on the batch handle (or, for a batch that does not exist
+// yet, where sos_last_error(NULL) finds it)
+template <typename F>
+int guarded_b(sos_batch *B, F &&f) {
+    try {
+        f();
+        return SOS_OK;
+    } catch (const Status &s) {
+        if (B) B->err = s.msg;
+        else g_setup_error = s.msg;
+        return s.code;
+    } catch (const std::bad_alloc &) {
+        if (B) B->err = "host allocation failed";
+        else g_setup_error = "host allocation failed";
         return SOS_E_NOMEM;
     }
 }
@@ -1071,7 +1090,7 @@ int sos_psd_factor(sos_work *w, int32_t block, int32_t dual, double *evals, doub
         if (!d_val || !d_vec) throw Status(SOS_E_NOMEM, "hipMalloc failed");
         RunParams rp = single_params(w, RUN_STEP, 0, 0, w->st.tol);
         if (sos_launch_psd_factor(w->threads, rp, block, dual, d_val, d_vec, w->stream))
-            throw Status(SOS_E_HIP, "factor launch failed");
+            throw Status(SOS_E_HIP, std::string("factor launch failed: ") + sos_launch_message());
         hip_check(hipMemcpyAsync(evals, d_val, sizeof(double) * N, hipMemcpyDeviceToHost, w->stream), "copy");
         hip_check(hipMemcpyAsync(evecs, d_vec, sizeof(double) * N * N, hipMemcpyDeviceToHost, w->stream), "copy");
         hip_check(hipStreamSynchronize(w->stream), "sync");
@@ -1099,7 +1118,7 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
     *out = nullptr;
     sos_batch *B = new (std::nothrow) sos_batch();
     if (!B) return SOS_E_NOMEM;
-    int rc = guarded(nullptr, [&] {
+    int rc = guarded_b(B, [&] {
         B->count = count;
         B->probs.assign(probs, probs + count);
         for (int i = 0; i < count; ++i)
@@ -1181,6 +1200,7 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         for (auto &e : B->evp) hip_check(hipEventCreate(&e), "event");
     });
     if (rc != SOS_OK) {
+        g_setup_error = B->err;   // the batch does not survive: sos_last_error(NULL) has the message
         if (B->stream) (void)hipStreamDestroy(B->stream);
         delete B;
         return rc;
@@ -1188,6 +1208,8 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
     *out = B;
     return SOS_OK;
 }
+
+const char *sos_batch_last_error(const sos_batch *B) { return B ? B->err.c_str() : g_setup_error.c_str(); }
 
 static RunParams batch_params(sos_batch *B, int mode, int iters, int min_iters, double tol) {
     RunParams rp{};
@@ -1217,12 +1239,12 @@ static RunParams batch_params(sos_batch *B, int mode, int iters, int min_iters, 
 
 static void enqueue_batch(sos_batch *B) {
     // the solve kernels stamp their own start / end (device wall clock), which also works in a graph
-    if (sos_launch_reset(B->d_counter, B->stream, B->d_ts)) throw Status(SOS_E_HIP, "reset launch failed");
+    if (sos_launch_reset(B->d_counter, B->stream, B->d_ts)) throw Status(SOS_E_HIP, std::string("reset launch failed: ") + sos_launch_message());
     if (B->fp64) {
         RunParams rp = batch_params(B, RUN_SOLVE, B->st.max_iters, 0, B->st.tol);
         rp.warm_budget = B->st.warm_budget;
         rp.ts = B->d_ts;
-        if (sos_launch_admm(1, B->threads, B->grid, rp, B->stream)) throw Status(SOS_E_HIP, "launch failed");
+        if (sos_launch_admm(1, B->threads, B->grid, rp, B->stream)) throw Status(SOS_E_HIP, std::string("launch failed: ") + sos_launch_message());
     } else {
         // FP32 phase: to tol, or until it stops improving; then FP64 for the rest of the budget
         RunParams rp = batch_params(B, RUN_SOLVE, B->st.max_iters, 0, B->st.tol);
@@ -1240,21 +1262,21 @@ static void enqueue_batch(sos_batch *B) {
                 B->used_one_launch = true;
                 return;
             }
-            if (rc != -1) throw Status(SOS_E_HIP, "launch failed");
+            if (rc != -1) throw Status(SOS_E_HIP, std::string("launch failed: ") + sos_launch_message());
         }
         B->used_one_launch = false;
-        if (sos_launch_admm(0, B->threads, B->grid, rp, B->stream)) throw Status(SOS_E_HIP, "launch failed");
+        if (sos_launch_admm(0, B->threads, B->grid, rp, B->stream)) throw Status(SOS_E_HIP, std::string("launch failed: ") + sos_launch_message());
         if (sos_launch_cast_state(B->d_desc, nullptr, B->count, 1, B->stream, B->max_len))
-            throw Status(SOS_E_HIP, "cast launch failed");
-        if (sos_launch_reset(B->d_counter, B->stream, B->d_ts + 2)) throw Status(SOS_E_HIP, "reset launch failed");
+            throw Status(SOS_E_HIP, std::string("cast launch failed: ") + sos_launch_message());
+        if (sos_launch_reset(B->d_counter, B->stream, B->d_ts + 2)) throw Status(SOS_E_HIP, std::string("reset launch failed: ") + sos_launch_message());
         rp2.ts = B->d_ts + 2;
-        if (sos_launch_admm(1, B->threads, B->grid, rp2, B->stream)) throw Status(SOS_E_HIP, "launch failed");
+        if (sos_launch_admm(1, B->threads, B->grid, rp2, B->stream)) throw Status(SOS_E_HIP, std::string("launch failed: ") + sos_launch_message());
     }
 }
 
 int sos_batch_solve(sos_batch *B, sos_info *infos) {
     if (!B || !infos) return SOS_E_INVAL;
-    int rc = guarded(nullptr, [&] {
+    int rc = guarded_b(B, [&] {
         // the handles' current iterate must sit in the copy the solve starts from
         for (sos_work *w : B->probs) {
             set_active(w, B->fp64 != 0);
@@ -1306,10 +1328,10 @@ int sos_batch_solve(sos_batch *B, sos_info *infos) {
 
 int sos_batch_reset(sos_batch *B) {
     if (!B) return SOS_E_INVAL;
-    return guarded(nullptr, [&] {
+    return guarded_b(B, [&] {
         for (sos_work *w : B->probs) hip_check(hipStreamSynchronize(w->stream), "sync");
         if (sos_launch_reset_state(B->d_desc, B->count, B->max_len, B->stream))
-            throw Status(SOS_E_HIP, "reset launch failed");
+            throw Status(SOS_E_HIP, std::string("reset launch failed: ") + sos_launch_message());
         hip_check(hipStreamSynchronize(B->stream), "sync");
         for (sos_work *w : B->probs) w->active64 = true;
     });
@@ -1317,14 +1339,14 @@ int sos_batch_reset(sos_batch *B) {
 
 int sos_batch_warm_start(sos_batch *B, const float *pred_dev, int64_t ld) {
     if (!B || !pred_dev || ld < 1) return SOS_E_INVAL;
-    return guarded(nullptr, [&] {
+    return guarded_b(B, [&] {
         for (sos_work *w : B->probs) {
             if (ld < (int64_t)w->nx + w->m) throw Status(SOS_E_INVAL, "prediction rows shorter than nx + m");
             hip_check(hipStreamSynchronize(w->stream), "sync");
         }
         RunParams rp = batch_params(B, RUN_SOLVE, 0, 0, B->st.tol);
         if (sos_launch_warm_start(B->fp64, B->threads, B->grid, rp, pred_dev, (long long)ld, B->stream))
-            throw Status(SOS_E_HIP, "warm start launch failed");
+            throw Status(SOS_E_HIP, std::string("warm start launch failed: ") + sos_launch_message());
         hip_check(hipStreamSynchronize(B->stream), "sync");
         for (sos_work *w : B->probs) w->active64 = B->fp64 != 0;
     });
@@ -1332,7 +1354,7 @@ int sos_batch_warm_start(sos_batch *B, const float *pred_dev, int64_t ld) {
 
 int sos_batch_export_solutions(sos_batch *B, float *out_dev, int64_t ld) {
     if (!B || !out_dev || ld < 1) return SOS_E_INVAL;
-    return guarded(nullptr, [&] {
+    return guarded_b(B, [&] {
         bool all64 = true;
         for (sos_work *w : B->probs) {
             if (ld < (int64_t)w->nx + w->m) throw Status(SOS_E_INVAL, "output rows shorter than nx + m");
@@ -1341,7 +1363,7 @@ int sos_batch_export_solutions(sos_batch *B, float *out_dev, int64_t ld) {
         }
         if (!all64) throw Status(SOS_E_STATE, "export needs the FP64 iterate (after a solve)");
         if (sos_launch_export(1, B->d_desc, B->count, out_dev, (long long)ld, B->max_len, B->stream))
-            throw Status(SOS_E_HIP, "export launch failed");
+            throw Status(SOS_E_HIP, std::string("export launch failed: ") + sos_launch_message());
         hip_check(hipStreamSynchronize(B->stream), "sync");
     });
 }

@@ -128,7 +128,9 @@ struct CoopCtl {
 // Largest number of workgroups of a cooperative launch (per-workgroup partial sums in the scratch).
 #define SOS_COOP_MAX_WG 1024
 
-// host-side launchers implemented in sos_kernels.hip
+// host-side launchers implemented in sos_kernels.hip; a launcher returning -4 leaves the reason
+// in sos_launch_message() (this thread)
+const char *sos_launch_message();
 int sos_launch_admm(int fp64, int threads, int grid, const RunParams &rp, void *stream);
 // the mixed form in one launch (FP32 phase, widening, FP64 phase per problem); threads 256 or
 // 512, else returns -1 and the caller launches the phases separately

@@ -17,6 +17,7 @@
 //            PSD part of w parked in v for the projection.
 // The identity u_hat_tau = omega_tau + theta follows from the rank-one formula:
 // zeta^T u_hat = zeta^T sigma - theta zeta^T h = zeta^T sigma / eta = theta.
+#include <cstdio>
 #include <mutex>
 #include <type_traits>
 #include <hip/hip_runtime.h>
@@ -1982,6 +1983,22 @@ __global__ void reset_state(const ProbDesc *probs, int count) {
     }
 }
 
+// Launch diagnostics: an error an earlier asynchronous call left pending is reported (not
+// cleared silently) before a launch, and a failed launch leaves its HIP error string.
+thread_local char g_launch_msg[256] = "";
+bool launch_precheck() {
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return true;
+    snprintf(g_launch_msg, sizeof(g_launch_msg), "HIP error pending from an earlier call: %s", hipGetErrorString(e));
+    return false;
+}
+int launch_result() {
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return 0;
+    snprintf(g_launch_msg, sizeof(g_launch_msg), "kernel launch: %s", hipGetErrorString(e));
+    return -4;
+}
+
 // Dynamic LDS layout for element type T: sigma, then the eigen region: the rows form's G, V,
 // partial records and sigma for blocks up to rows_nmax (eig_wave 2); for the lane-group form,
 // G and V (both N x N) up to lds_nmax, or G alone up to lds_nmax_g (larger blocks work in
@@ -2026,7 +2043,7 @@ int launch_t(int grid, const RunParams &rp_in, hipStream_t st) {
         (void)hipGetLastError();   // not every runtime needs (or accepts during capture) the attribute
     }
     hipLaunchKernelGGL((admm_persistent<T, NT>), dim3(grid), dim3(NT), lds, st, rp);
-    return hipGetLastError() == hipSuccess ? 0 : -4;
+    return launch_result();
 }
 
 template <int NT>
@@ -2044,10 +2061,12 @@ int launch_mixed(int grid, const RunParams &rp32_in, const RunParams &rp64_in, h
         (void)hipGetLastError();
     }
     hipLaunchKernelGGL((admm_mixed<NT>), dim3(grid), dim3(NT), lds, st, rp32, rp64);
-    return hipGetLastError() == hipSuccess ? 0 : -4;
+    return launch_result();
 }
 
 }   // namespace
+
+const char *sos_launch_message() { return g_launch_msg; }
 
 int sos_launch_admm_mixed(int threads, int grid, const RunParams &rp32, const RunParams &rp64, void *stream) {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -2081,9 +2100,9 @@ int sos_launch_admm(int fp64, int threads, int grid, const RunParams &rp, void *
 }
 
 int sos_launch_reset(int *counter, void *stream, unsigned long long *ts) {
-    (void)hipGetLastError();
+    if (!launch_precheck()) return -4;
     hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), counter, ts);
-    return hipGetLastError() == hipSuccess ? 0 : -4;
+    return launch_result();
 }
 
 int sos_launch_cast_state(const ProbDesc *probs_dev, const int *ids, int count, int to64, void *stream,
@@ -2092,10 +2111,10 @@ int sos_launch_cast_state(const ProbDesc *probs_dev, const int *ids, int count, 
     int gx = (max_len + 255) / 256;
     if (gx > 64) gx = 64;
     if (gx < 1) gx = 1;
-    (void)hipGetLastError();
+    if (!launch_precheck()) return -4;
     hipLaunchKernelGGL(cast_state, dim3(gx, count), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), probs_dev,
                        ids, count, to64);
-    return hipGetLastError() == hipSuccess ? 0 : -4;
+    return launch_result();
 }
 
 int sos_launch_reset_state(const ProbDesc *probs_dev, int count, int max_len, void *stream) {
@@ -2103,10 +2122,10 @@ int sos_launch_reset_state(const ProbDesc *probs_dev, int count, int max_len, vo
     int gx = (max_len + 255) / 256;
     if (gx > 64) gx = 64;
     if (gx < 1) gx = 1;
-    (void)hipGetLastError();
+    if (!launch_precheck()) return -4;
     hipLaunchKernelGGL(reset_state, dim3(gx, count), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), probs_dev,
                        count);
-    return hipGetLastError() == hipSuccess ? 0 : -4;
+    return launch_result();
 }
 
 int sos_launch_warm_start(int fp64, int threads, int grid, const RunParams &rp_in, const float *pred, long long ld,
@@ -2115,7 +2134,7 @@ int sos_launch_warm_start(int fp64, int threads, int grid, const RunParams &rp_i
     if (grid < 1) return -1;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     size_t lds = 0;
-    (void)hipGetLastError();
+    if (!launch_precheck()) return -4;
 #define SOS_WS(TT, NTT)                                                                                          \
     {                                                                                                           \
         lds_layout<TT>(rp.eig_ld, rp.lds_budget, NTT / 64, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds,      \
@@ -2134,7 +2153,7 @@ int sos_launch_warm_start(int fp64, int threads, int grid, const RunParams &rp_i
         if (threads == 256) SOS_WS(float, 256) else if (threads == 512) SOS_WS(float, 512) else if (threads == 128) SOS_WS(float, 128) else SOS_WS(float, 64)
     }
 #undef SOS_WS
-    return hipGetLastError() == hipSuccess ? 0 : -4;
+    return launch_result();
 }
 
 int sos_static_scratch(void **ptr) {
@@ -2196,7 +2215,7 @@ int sos_launch_admm_coop(int threads, int grid, const RunParams &rp_in, CoopCtl 
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (grid < 1 || grid > SOS_COOP_MAX_WG || bcols < 1) return -1;
     const size_t lds = coop_lds_bytes(rp, bcols);
-    (void)hipGetLastError();
+    if (!launch_precheck()) return -4;
     hipLaunchKernelGGL(reset_coop, dim3(1), dim3(64), 0, st, ctl);
     void *args[] = {&rp, &ctl, &scratch, &bcols};
     hipError_t e;
@@ -2213,6 +2232,7 @@ int sos_launch_admm_coop(int threads, int grid, const RunParams &rp_in, CoopCtl 
     }
     if (e != hipSuccess) {
         (void)hipGetLastError();
+        snprintf(g_launch_msg, sizeof(g_launch_msg), "cooperative launch: %s", hipGetErrorString(e));
         return -4;
     }
     return 0;
@@ -2223,7 +2243,7 @@ int sos_launch_psd_factor(int threads, const RunParams &rp_in, int blk, int dual
     RunParams rp = rp_in;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     size_t lds = 0;
-    (void)hipGetLastError();
+    if (!launch_precheck()) return -4;
 #define SOS_PF(NTT)                                                                                               \
     {                                                                                                            \
         lds_layout<double>(rp.eig_ld, rp.lds_budget, NTT / 64, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds,   \
@@ -2244,7 +2264,7 @@ int sos_launch_psd_factor(int threads, const RunParams &rp_in, int blk, int dual
         default: return -1;
     }
 #undef SOS_PF
-    return hipGetLastError() == hipSuccess ? 0 : -4;
+    return launch_result();
 }
 
 int sos_launch_export(int fp64, const ProbDesc *probs, int count, float *out, long long ld, int max_len, void *stream) {
@@ -2252,12 +2272,12 @@ int sos_launch_export(int fp64, const ProbDesc *probs, int count, float *out, lo
     int gx = (max_len + 255) / 256;
     if (gx > 64) gx = 64;
     if (gx < 1) gx = 1;
-    (void)hipGetLastError();
+    if (!launch_precheck()) return -4;
     if (fp64)
         hipLaunchKernelGGL(export_solution<double>, dim3(gx, count), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
                            probs, count, out, ld);
     else
         hipLaunchKernelGGL(export_solution<float>, dim3(gx, count), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
                            probs, count, out, ld);
-    return hipGetLastError() == hipSuccess ? 0 : -4;
+    return launch_result();
 }

@@ -158,6 +158,16 @@ __global__ void adam_step(long long n, float *__restrict__ p, const float *__res
 }
 
 // Y = Y * scale[j] + shift[j]
+// dst[r][:] = src[rows[r]][:] for r < nrows (row-major, cols columns): a mini-batch gather
+__global__ void gather_rows(const float *__restrict__ src, int cols, const int *__restrict__ rows, int nrows,
+                            float *__restrict__ dst) {
+    const long long total = (long long)nrows * cols;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+        const long long r = i / cols, c = i - r * cols;
+        dst[i] = src[(long long)rows[r] * cols + c];
+    }
+}
+
 __global__ void affine_cols(int M, int N, float *__restrict__ Y, const float *__restrict__ scale,
                             const float *__restrict__ shift) {
     const long long total = (long long)M * N;
@@ -184,6 +194,7 @@ struct sos_mlp {
     float *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr, *Y = nullptr;
     float *dY = nullptr, *dH = nullptr, *dZ = nullptr;
     float *oscale = nullptr, *oshift = nullptr;
+    float *Xg = nullptr, *Tg = nullptr;                                 // gathered mini-batch (train_step_rows)
     double *part = nullptr, *loss = nullptr;
     long long step = 0;
     std::string err;
@@ -281,7 +292,8 @@ int sos_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t max_ba
                 ok(hipMalloc(&m->H2, bh * 4)) && ok(hipMalloc(&m->Y, bo * 4)) && ok(hipMalloc(&m->dY, bo * 4)) &&
                 ok(hipMalloc(&m->dH, bh * 4)) && ok(hipMalloc(&m->dZ, bh * 4)) &&
                 ok(hipMalloc(&m->oscale, (long long)n_out * 4)) && ok(hipMalloc(&m->oshift, (long long)n_out * 4)) &&
-                ok(hipMalloc(&m->part, 256 * 8)) && ok(hipMalloc(&m->loss, 8));
+                ok(hipMalloc(&m->part, 256 * 8)) && ok(hipMalloc(&m->loss, 8)) &&
+                ok(hipMalloc(&m->Xg, (long long)max_batch * n_in * 4)) && ok(hipMalloc(&m->Tg, bo * 4));
     if (!good) {
         sos_mlp_free(m);
         return SOS_E_NOMEM;
@@ -346,6 +358,20 @@ int sos_mlp_gradient(sos_mlp *m, const float *X_dev, const float *T_dev, int32_t
     });
 }
 
+int sos_mlp_train_step_rows(sos_mlp *m, const float *X_dev, const float *T_dev, const int32_t *rows_dev, int32_t batch,
+                            float lr, double *loss_host) {
+    if (!m || !X_dev || !T_dev || !rows_dev || batch < 1 || batch > m->cap || !(lr > 0.f)) return SOS_E_INVAL;
+    const int rc = guard(m, [&] {
+        hipLaunchKernelGGL(gather_rows, dim3(grid_for((long long)batch * m->nin)), dim3(256), 0, m->st, X_dev, m->nin,
+                           rows_dev, batch, m->Xg);
+        hipLaunchKernelGGL(gather_rows, dim3(grid_for((long long)batch * m->nout)), dim3(256), 0, m->st, T_dev, m->nout,
+                           rows_dev, batch, m->Tg);
+        return SOS_OK;
+    });
+    if (rc != SOS_OK) return rc;
+    return sos_mlp_train_step(m, m->Xg, m->Tg, batch, lr, loss_host);
+}
+
 int sos_mlp_train_step(sos_mlp *m, const float *X_dev, const float *T_dev, int32_t batch, float lr, double *loss_host) {
     if (!m || !X_dev || !T_dev || batch < 1 || batch > m->cap || !(lr > 0.f)) return SOS_E_INVAL;
     return guard(m, [&] {
@@ -369,7 +395,8 @@ void sos_mlp_free(sos_mlp *m) {
     if (m->st) (void)hipStreamSynchronize(m->st);
     for (void *p : {(void *)m->P, (void *)m->G, (void *)m->Mm, (void *)m->Vv, (void *)m->Z1, (void *)m->H1,
                     (void *)m->Z2, (void *)m->H2, (void *)m->Y, (void *)m->dY, (void *)m->dH, (void *)m->dZ,
-                    (void *)m->oscale, (void *)m->oshift, (void *)m->part, (void *)m->loss})
+                    (void *)m->oscale, (void *)m->oshift, (void *)m->part, (void *)m->loss, (void *)m->Xg,
+                    (void *)m->Tg})
         if (p) (void)hipFree(p);
     delete m;
 }

@@ -7,8 +7,10 @@ The network and the solver run in libsos.so: this module moves arrays between th
    library's layout; instances the solver reports SOLVED are kept, minus those whose
    solution norm is far above the median (training_mask).
 2. Training: the device MLP (sos_mlp_*) on standardised targets, mini-batch Adam.
-   The standardisation (per-output mean and spread of the training targets) is data
-   preparation done once; the network's output layer undoes it on the device.
+   The standardisation (per-output mean and spread of the training targets) and the
+   choice of training rows are data preparation done once on the host (numpy); the
+   mini-batches are gathered by index in the library, and the network's output layer
+   undoes the standardisation on the device.
 3. Use: predict (xi, y) for new instances, sos_batch_warm_start makes the prediction
    consistent with the cones (u = (P_K(xi), y, 1), v = (P_K*(c - A^T y), 0, 0)), the
    batch is solved, and every problem that the warm start does not bring to a
@@ -25,15 +27,14 @@ import numpy as np
 from . import binding as B
 
 
-def training_mask(T, factor: float = 3.0):
-    """Rows of the exported solutions that train the model: those whose norm is at most
-    `factor` times the median norm.  Instances close to infeasibility end with a tiny tau,
-    so their normalised solutions are huge (norms up to hundreds of times the median);
-    left in, they dominate the target statistics and the network predicts neither them
-    nor the rest."""
-    import torch
-    nrm = torch.linalg.vector_norm(T.double(), dim=1)
-    return nrm <= factor * nrm.median()
+def training_mask(T_host: np.ndarray, factor: float = 3.0) -> np.ndarray:
+    """Rows of the exported solutions (host array) that train the model: those whose norm is
+    at most `factor` times the median norm.  Instances close to infeasibility end with a tiny
+    tau, so their normalised solutions are huge (norms up to hundreds of times the median);
+    left in, they dominate the target statistics and the network predicts neither them nor
+    the rest."""
+    nrm = np.linalg.norm(np.asarray(T_host, dtype=np.float64), axis=1)
+    return nrm <= factor * np.median(nrm)
 
 
 def export_solutions(batch: "B.Batch", layout: int):
@@ -67,27 +68,30 @@ class WarmStartModel:
         self.mu = np.zeros(n_out, dtype=np.float32)
         self.sd = np.ones(n_out, dtype=np.float32)
 
-    def fit(self, X, T, epochs: int = 60, batch: int = 256, lr: float = 1e-3, seed: int = 0,
-            log=None) -> List[float]:
-        """X: (S, n_in) float32 cuda tensor; T: (S, n_out) float32 cuda tensor (raw targets)."""
+    def fit(self, X_host: np.ndarray, T_host: np.ndarray, rows: Optional[np.ndarray] = None, epochs: int = 60,
+            batch: int = 256, lr: float = 1e-3, seed: int = 0, log=None) -> List[float]:
+        """X_host: (S, n_in), T_host: (S, n_out) host arrays (raw targets); rows: the rows to
+        train on (default all).  The standardisation is computed on the host over those rows,
+        the data go to the device once, and each mini-batch is a slice of a shuffled index list
+        that the library gathers (sos_mlp_train_step_rows)."""
         import torch
-        Tn_host = T.cpu().numpy().astype(np.float64)
-        self.mu = Tn_host.mean(axis=0).astype(np.float32)
-        sd = Tn_host.std(axis=0)
+        rows = np.arange(len(X_host)) if rows is None else np.asarray(rows)
+        Tsel = np.asarray(T_host, dtype=np.float64)[rows]
+        self.mu = Tsel.mean(axis=0).astype(np.float32)
+        sd = Tsel.std(axis=0)
         self.sd = np.where(sd > 1e-8, sd, 1.0).astype(np.float32)
-        Tn = ((T - torch.from_numpy(self.mu).cuda()) / torch.from_numpy(self.sd).cuda()).contiguous()
+        Tn_host = ((np.asarray(T_host, dtype=np.float64) - self.mu) / self.sd).astype(np.float32)
+        X = torch.from_numpy(np.ascontiguousarray(X_host, dtype=np.float32)).cuda()
+        Tn = torch.from_numpy(np.ascontiguousarray(Tn_host)).cuda()
         rng = np.random.default_rng(seed)
-        S = X.shape[0]
+        S = len(rows)
         losses = []
         for ep in range(epochs):
-            perm = torch.from_numpy(rng.permutation(S)).cuda()
+            perm = torch.from_numpy(rows[rng.permutation(S)].astype(np.int32)).cuda()
             tot, cnt = 0.0, 0
             for i in range(0, S - batch + 1, batch):
-                idx = perm[i:i + batch]
-                Xb = X.index_select(0, idx).contiguous()
-                Tb = Tn.index_select(0, idx).contiguous()
                 want = (i + batch > S - batch)
-                L = self.net.train_step(Xb, Tb, lr, want_loss=want)
+                L = self.net.train_step_rows(X, Tn, perm[i:i + batch], lr, want_loss=want)
                 if want:
                     tot, cnt = tot + L, cnt + 1
             losses.append(tot / max(cnt, 1))

@@ -104,13 +104,12 @@ def test_learned_warm_start_gain(env):
     tw = [B.setup_problem(F.lyapunov(s), st) for s in train]
     infos, sol, bt = W.cold_solve_batch(tw)
     keep = [i for i, inf in enumerate(infos) if inf["status"] == B.SOS_SOLVED]
-    Xtr = _dev(torch, np.stack([F.lyapunov_features(train[i]) for i in keep]))
-    Ttr = sol[torch.tensor(keep, device="cuda")].contiguous()
-    mask = W.training_mask(Ttr)
-    Xtr, Ttr = Xtr[mask].contiguous(), Ttr[mask].contiguous()
-    print(f"[warm] training set: {len(keep)}/{len(train)} solved cold, {int(mask.sum())} kept", flush=True)
+    Xtr = np.stack([F.lyapunov_features(train[i]) for i in keep]).astype(np.float32)
+    Ttr = sol.cpu().numpy()[keep]
+    rows = np.nonzero(W.training_mask(Ttr))[0]
+    print(f"[warm] training set: {len(keep)}/{len(train)} solved cold, {len(rows)} kept", flush=True)
     model = W.WarmStartModel(Xtr.shape[1], Ttr.shape[1], hidden=512, max_batch=4096, seed=0)
-    losses = model.fit(Xtr, Ttr, epochs=60, batch=128, lr=1e-3, log=lambda m: print(m, flush=True))
+    losses = model.fit(Xtr, Ttr, rows=rows, epochs=60, batch=128, lr=1e-3, log=lambda m: print(m, flush=True))
     assert losses[-1] < 0.5 * losses[0]
     # held-out: cold vs warm
     probs = [F.lyapunov(s) for s in test]
@@ -217,3 +216,37 @@ def test_failed_warm_start_restarts_cold_in_the_same_launch(env):
         assert np.array_equal(uw, uc) and np.array_equal(vw, vc)
     bc.free()
     bw.free()
+
+
+def test_train_step_rows_equals_train_step_on_gathered_rows(env):
+    # the library's index gather gives bitwise the same Adam steps as rows gathered on the host
+    B, torch = env
+    rng = np.random.default_rng(7)
+    nin, nh, nout, S, bs = 9, 32, 11, 40, 8
+    X = rng.standard_normal((S, nin)).astype(np.float32)
+    T = rng.standard_normal((S, nout)).astype(np.float32)
+    p0 = (rng.standard_normal(nin * nh + nh + nh * nh + nh + nh * nout + nout) * 0.2).astype(np.float32)
+    a, b = B.MLP(nin, nh, nout, 64), B.MLP(nin, nh, nout, 64)
+    a.set_params(p0)
+    b.set_params(p0)
+    Xd, Td = _dev(torch, X), _dev(torch, T)
+    for step in range(3):
+        rows = rng.permutation(S)[:bs].astype(np.int32)
+        la = a.train_step_rows(Xd, Td, torch.from_numpy(rows).cuda(), 1e-2, want_loss=True)
+        lb = b.train_step(_dev(torch, X[rows]), _dev(torch, T[rows]), 1e-2, want_loss=True)
+        assert la == lb
+    assert np.array_equal(a.get_params(), b.get_params())
+
+
+def test_batch_errors_carry_their_message(env):
+    B, torch = env
+    works = [B.setup_problem(F.lyapunov(s)) for s in (0, 1)]
+    bt = B.sos_batch_setup(works)
+    short = torch.zeros((2, 8), dtype=torch.float32, device="cuda")
+    with pytest.raises(B.SosError) as e:
+        B.sos_batch_warm_start(bt, short, 8)
+    assert e.value.code == B.SOS_E_INVAL and "shorter than nx + m" in str(e.value)
+    bt.free()
+    with pytest.raises(B.SosError) as e:
+        B.sos_batch_setup(works, '{"block_threads": 96}')
+    assert "block_threads" in str(e.value)
