@@ -40,6 +40,8 @@ constexpr int kLanesPerPair[7] = {16, 16, 8, 8, 16, 16, 16};
 constexpr int kCoopNmin = 128;
 // columns per Jacobi block of the multi-workgroup eigensolver (fewer when LDS is short)
 constexpr int kCoopBcols = 8;
+// the lane-group form's sweep order when G and V sit in LDS: 8 = block-cyclic, 0 = cyclic
+constexpr int kJacBlock = 8;
 // mixed form: the FP32 phase hands over after this many residual checks without a 10 % gain.
 // An FP32-stored iterate has a residual floor of about eps_32 |A| |y| / tau (above 1e-4 on the
 // Lyapunov family), so the hand-over should come soon after the floor is reached.
@@ -148,6 +150,7 @@ struct sos_batch {
     int warm_eig = 1, lds_budget = 0, eig_wave = 2, rows_nmin = 0;
     double jacobi_tol64 = 0.0;   // Jacobi tolerance of the mixed form's FP64 phase
     int stall_checks = 0;        // mixed form: checks without progress before the FP64 phase
+    int jac_block = 8;           // lane-group form's sweep order (see RunParams::jac_block)
     int one_launch = 1;   // mixed form: both phases in one launch (threads 256 or 512)
     bool used_one_launch = false;
     int gs_bucket[7] = {16, 16, 16, 16, 16, 16, 16};
@@ -679,6 +682,7 @@ RunParams single_params(sos_work *w, int mode, int iters, int min_iters, double 
     for (int i = 0; i < 7; ++i) rp.gs_bucket[i] = kLanesPerPair[i];
     rp.eig_wave = w->st.eig_form == 2 ? 0 : 2;
     rp.rows_nmin = w->st.eig_form == 0 ? kRowsNmin : 0;
+    rp.jac_block = kJacBlock;
     return rp;
 }
 
@@ -1137,6 +1141,8 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         B->rows_nmin = (int)json_num(schedule_json, "rows_nmin", kRowsNmin);
         B->jacobi_tol64 = json_num(schedule_json, "fp64_jacobi_tol", kMixedJacobiTol64);
         B->stall_checks = (int)json_num(schedule_json, "stall_checks", kStallChecks);
+        B->jac_block = (int)json_num(schedule_json, "jac_block", kJacBlock);
+        if (B->jac_block != 0 && B->jac_block != 8) throw Status(SOS_E_INVAL, "schedule jac_block must be 0 or 8");
         if (B->stall_checks < 1) throw Status(SOS_E_INVAL, "schedule stall_checks must be >= 1");
         if (!(B->jacobi_tol64 >= 0.0 && B->jacobi_tol64 < 1e-3))
             throw Status(SOS_E_INVAL, "schedule fp64_jacobi_tol must be in [0, 1e-3)");
@@ -1233,6 +1239,7 @@ static RunParams batch_params(sos_batch *B, int mode, int iters, int min_iters, 
     rp.eig_wave = B->eig_wave;
     rp.rows_nmin = B->rows_nmin;
     rp.lds_budget = B->lds_budget;
+    rp.jac_block = B->jac_block;
     for (int i = 0; i < 7; ++i) rp.gs_bucket[i] = B->gs_bucket[i];
     return rp;
 }

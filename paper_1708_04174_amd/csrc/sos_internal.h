@@ -112,6 +112,8 @@ struct RunParams {
                             // N < 32, < 64, < 96, < 128, < 192, < 256, >= 256
     int stall_checks;       // > 0: stop a problem that stopped improving (see the kernel) this many checks in a row
     double jacobi_tol;      // relative coupling a Jacobi pair must exceed to be rotated (0: 16 eps of the type)
+    int jac_block;          // 8: the lane-group form sweeps in the block-cyclic order when G and V sit in
+                            //    LDS (a workgroup barrier per block round); 0: the cyclic order
     unsigned long long *ts; // optional [start, end] wall-clock stamps of the launch (min / max over workgroups)
 };
 

@@ -716,10 +716,57 @@ __device__ __forceinline__ void mfma_rebuild(VP V, int ldv, SP sig, int N, T *__
 // barrier per round.  With a cached V from the previous ADMM iteration (warm) the sweeps
 // start from G = W V, which is nearly orthogonal once the iterates settle.
 // G, V: column-major N x N (column j at j*ld), in LDS or global scratch; Tm: N x N global.
+// Between Jacobi rounds, within a wavefront: a code-motion barrier only.  A wavefront's LDS
+// operations are performed in issue order, so a read issued after a write (by any lane of
+// the same wavefront) returns the written value without waiting for the write to finish.
+__device__ __forceinline__ void wave_order() { __builtin_amdgcn_wave_barrier(); }
+
+// Block-cyclic sweep of the lane-group form (G and V in LDS): the columns form blocks of 8;
+// first every block's own pairs (a wavefront per block, four 8-lane groups per round of the
+// block's round-robin), then block rounds over pairs of blocks (round-robin of the blocks), a
+// wavefront per block pair covering its 64 cross pairs in 8 steps of 8 disjoint pairs (group g
+// rotates columns 8P + g and 8Q + (g + s) mod 8 in step s).  Every column pair meets once per
+// sweep, as in the cyclic order, but only the block rounds end in a workgroup barrier (N / 8 + 1
+// per sweep instead of N - 1): inside a block round the wavefront's own LDS order suffices.
+// Returns 1 if some rotation had relative coupling above sqrt(tol).
+template <typename T, int NT, typename LP>
+__device__ __forceinline__ int block_cyclic_sweep(LP G, LP V, int ld, int N, T tol, T atol) {
+    constexpr int NW = NT / 64;
+    const int wid = threadIdx.x >> 6, grp = (threadIdx.x & 63) >> 3;
+    const int nb = (N + 7) >> 3, nbp = nb + (nb & 1);
+    int big = 0;
+    for (int B = wid; B < nb; B += NW) {
+        const int c0 = B * 8, c = N - c0 < 8 ? N - c0 : 8, M = c + (c & 1);
+        for (int r = 0; r < M - 1; ++r) {
+            if (grp < M / 2) {
+                int p, q;
+                rr_pair(r, grp, M, p, q);
+                if (q < c && os_rotate_pair<T, 8, LP, LP>(G, ld, V, ld, N, c0 + p, c0 + q, tol, atol) == 2) big = 1;
+            }
+            wave_order();
+        }
+    }
+    __syncthreads();
+    for (int R = 0; R < nbp - 1; ++R) {
+        for (int pk = wid; pk < nbp / 2; pk += NW) {
+            int P, Q;
+            rr_pair(R, pk, nbp, P, Q);
+            if (Q >= nb) continue;
+            for (int st = 0; st < 8; ++st) {
+                const int p = P * 8 + grp, q = Q * 8 + ((grp + st) & 7);
+                if (p < N && q < N && os_rotate_pair<T, 8, LP, LP>(G, ld, V, ld, N, p, q, tol, atol) == 2) big = 1;
+                wave_order();
+            }
+        }
+        __syncthreads();
+    }
+    return big;
+}
+
 template <typename T, int NT, typename GP, typename VP>
 __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ us, int N, T *__restrict__ Vs, bool warm, GP G,
                               VP V, int ld, T *__restrict__ Tm, typename Lds<T>::type *s_sig, const EigScratch &sc,
-                              int max_sweeps, int gs = 16) {
+                              int max_sweeps, int gs = 16, int jblock = 0) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     constexpr int NW = NT / 64;
     if (N == 1) {
@@ -793,8 +840,12 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
         // the sweep is the last: cyclic Jacobi converges quadratically, so what such a sweep
         // leaves is coupling of order tol, which the next sweep would not rotate
         int big = 0;
-        // lanes per column pair: a tile choice per block-size bucket (autotuned)
-        if (gs == 8) {
+        constexpr bool kBothLds = std::is_same<GP, typename Lds<T>::type *>::value && std::is_same<VP, GP>::value;
+        // lanes per column pair: a tile choice per block-size bucket (autotuned), or the
+        // block-cyclic order (G and V in LDS)
+        if (kBothLds && jblock == 8) {
+            if constexpr (kBothLds) big = block_cyclic_sweep<T, NT>(G, V, ld, N, tol, atol);
+        } else if (gs == 8) {
             const int grp = tid / 8;
             for (int r = 0; r < M - 1; ++r) {
                 for (int kk = grp; kk < H; kk += NT / 8) {
@@ -866,11 +917,6 @@ template <> struct V16<double> {
 template <typename T> __device__ __forceinline__ T hsum(typename V16<T>::v x);
 template <> __device__ __forceinline__ float hsum<float>(V16<float>::v x) { return (x.x + x.y) + (x.z + x.w); }
 template <> __device__ __forceinline__ double hsum<double>(V16<double>::v x) { return x.x + x.y; }
-
-// Between Jacobi rounds, within a wavefront: a code-motion barrier only.  A wavefront's LDS
-// operations are performed in issue order, so a read issued after a write (by any lane of
-// the same wavefront) returns the written value without waiting for the write to finish.
-__device__ __forceinline__ void wave_order() { __builtin_amdgcn_wave_barrier(); }
 
 // ----------------------------------------------------------------------------- PSD projection, rows per wavefront
 // Same projection again, with the rows of the column-major N x N matrices G and V split
@@ -1334,7 +1380,7 @@ __device__ __noinline__ int run_phase(const ProbDesc &P, const RunParams &rp, ch
             T *g1 = Tm + (long long)P.nmax * P.nmax, *g2 = g1 + (long long)P.nmax * P.nmax;
             if (N <= rp.lds_nmax)        // G and V in LDS, columns padded (lds_ld)
                 project_block<T, NT>(v + off, u + off, N, vc, wm, s_mat, s_mat + (long long)N * lds_ld(N), lds_ld(N),
-                                     Tm, s_sig, sc, rp.max_sweeps, gs);
+                                     Tm, s_sig, sc, rp.max_sweeps, gs, rp.jac_block);
             else if (N <= rp.lds_nmax_g)  // G in LDS, V in global scratch
                 project_block<T, NT>(v + off, u + off, N, vc, wm, s_mat, g1, ld, Tm, s_sig, sc, rp.max_sweeps, gs);
             else                          // both in global scratch
