@@ -721,6 +721,85 @@ __device__ __forceinline__ void mfma_rebuild(VP V, int ldv, SP sig, int N, T *__
 // the same wavefront) returns the written value without waiting for the write to finish.
 __device__ __forceinline__ void wave_order() { __builtin_amdgcn_wave_barrier(); }
 
+// Lane rotation by one 8-lane group across the wavefront: lane l takes lane (l + 8) mod 64.
+__device__ __forceinline__ float next_group(float x) { return __shfl(x, (int)((threadIdx.x + 8) & 63), 64); }
+__device__ __forceinline__ double next_group(double x) { return __shfl(x, (int)((threadIdx.x + 8) & 63), 64); }
+
+// The 64 cross pairs of blocks P and Q (8 columns each) by one wavefront, columns in registers:
+// group g keeps column 8P + g of G and V (RPL rows per lane) for the whole round and starts with
+// column 8Q + g; after each step every group passes its Q column to the group before it (lanes
+// - 8, wrapping), so in step s group g holds Q column (g + s) mod 8, and after the last step column
+// (g + 7) mod 8, which it writes back.  LDS is read and written once per round instead of per step.
+// Columns and rows at or past N are zero (their products vanish; such columns are never rotated).
+// Returns 1 if a rotation had relative coupling above sqrt(tol).
+template <typename T, int RPL, typename LP>
+__device__ __forceinline__ int cross_block_regs(LP G, LP V, int ld, int N, int P, int Q, T tol, T atol) {
+    const int gl = threadIdx.x & 7, grp = (threadIdx.x & 63) >> 3;
+    const int p = P * 8 + grp;
+    const bool pok = p < N;
+    int qc = Q * 8 + grp;   // the Q column this group holds
+    T xp[RPL], yp[RPL], xq[RPL], yq[RPL];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+        const int i = gl + 8 * t;
+        const bool iok = i < N;
+        xp[t] = (pok && iok) ? G[(long long)p * ld + i] : (T)0;
+        yp[t] = (pok && iok) ? V[(long long)p * ld + i] : (T)0;
+        xq[t] = (qc < N && iok) ? G[(long long)qc * ld + i] : (T)0;
+        yq[t] = (qc < N && iok) ? V[(long long)qc * ld + i] : (T)0;
+    }
+    int big = 0;
+    const T tol2 = tol * tol, atol2 = atol * atol;
+#pragma unroll 1
+    for (int st = 0; st < 8; ++st) {
+        T al = 0, be = 0, ga = 0;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+            al += xp[t] * xp[t];
+            be += xq[t] * xq[t];
+            ga += xp[t] * xq[t];
+        }
+        al = group_allsum<8>(al);
+        be = group_allsum<8>(be);
+        ga = group_allsum<8>(ga);
+        T cc, ss;
+        if (jacobi_rot<T>(al, be, ga, tol2, atol2, cc, ss)) {
+            if (ga * ga > tol * (al * be)) big = 1;
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+                const T a = xp[t], b = xq[t], c = yp[t], d = yq[t];
+                xp[t] = cc * a - ss * b;
+                xq[t] = ss * a + cc * b;
+                yp[t] = cc * c - ss * d;
+                yq[t] = ss * c + cc * d;
+            }
+        }
+        if (st < 7) {
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+                xq[t] = next_group(xq[t]);
+                yq[t] = next_group(yq[t]);
+            }
+        }
+    }
+    qc = Q * 8 + ((grp + 7) & 7);
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+        const int i = gl + 8 * t;
+        if (i < N) {
+            if (pok) {
+                G[(long long)p * ld + i] = xp[t];
+                V[(long long)p * ld + i] = yp[t];
+            }
+            if (qc < N) {
+                G[(long long)qc * ld + i] = xq[t];
+                V[(long long)qc * ld + i] = yq[t];
+            }
+        }
+    }
+    return big;
+}
+
 // Block-cyclic sweep of the lane-group form (G and V in LDS): the columns form blocks of 8;
 // first every block's own pairs (a wavefront per block, four 8-lane groups per round of the
 // block's round-robin), then block rounds over pairs of blocks (round-robin of the blocks), a
@@ -728,6 +807,8 @@ __device__ __forceinline__ void wave_order() { __builtin_amdgcn_wave_barrier(); 
 // rotates columns 8P + g and 8Q + (g + s) mod 8 in step s).  Every column pair meets once per
 // sweep, as in the cyclic order, but only the block rounds end in a workgroup barrier (N / 8 + 1
 // per sweep instead of N - 1): inside a block round the wavefront's own LDS order suffices.
+// Up to N = 32 a cross round keeps its columns in registers (cross_block_regs): faster there;
+// for larger blocks the fixed rows per lane and the register pressure made it slower than LDS.
 // Returns 1 if some rotation had relative coupling above sqrt(tol).
 template <typename T, int NT, typename LP>
 __device__ __forceinline__ int block_cyclic_sweep(LP G, LP V, int ld, int N, T tol, T atol) {
@@ -752,6 +833,10 @@ __device__ __forceinline__ int block_cyclic_sweep(LP G, LP V, int ld, int N, T t
             int P, Q;
             rr_pair(R, pk, nbp, P, Q);
             if (Q >= nb) continue;
+            if (N <= 32) {
+                big |= cross_block_regs<T, 4>(G, V, ld, N, P, Q, tol, atol);
+                continue;
+            }
             for (int st = 0; st < 8; ++st) {
                 const int p = P * 8 + grp, q = Q * 8 + ((grp + st) & 7);
                 if (p < N && q < N && os_rotate_pair<T, 8, LP, LP>(G, ld, V, ld, N, p, q, tol, atol) == 2) big = 1;
