@@ -727,26 +727,29 @@ __device__ __forceinline__ double next_group(double x) { return __shfl(x, (int)(
 
 // The 64 cross pairs of blocks P and Q (8 columns each) by one wavefront, columns in registers:
 // group g keeps column 8P + g of G and V (RPL rows per lane) for the whole round and starts with
-// column 8Q + g; after each step every group passes its Q column to the group before it (lanes
-// - 8, wrapping), so in step s group g holds Q column (g + s) mod 8, and after the last step column
-// (g + 7) mod 8, which it writes back.  LDS is read and written once per round instead of per step.
-// Columns and rows at or past N are zero (their products vanish; such columns are never rotated).
-// Returns 1 if a rotation had relative coupling above sqrt(tol).
-template <typename T, int RPL, typename LP>
+// column 8Q + g; after each step every group passes its column of Q to the group before it (lane
+// l takes lane l + 8, wrapping), so in step s group g holds column 8Q + (g + s) mod 8, and after
+// the last step column 8Q + (g + 7) mod 8, which it writes back.  With VQ the V column of Q travels
+// the same way; without, it stays in LDS and only a step that rotates reads and writes it (the
+// group that owns it next is in the same wavefront, whose LDS accesses are performed in order):
+// fewer shuffles when few pairs rotate, LDS traffic when many do.  Columns and rows at or past N
+// are zero (their products vanish; such columns are never rotated).  Returns 1 if a rotation had
+// relative coupling above sqrt(tol).
+template <typename T, int RPL, bool VQ, typename LP>
 __device__ __forceinline__ int cross_block_regs(LP G, LP V, int ld, int N, int P, int Q, T tol, T atol) {
     const int gl = threadIdx.x & 7, grp = (threadIdx.x & 63) >> 3;
     const int p = P * 8 + grp;
     const bool pok = p < N;
-    int qc = Q * 8 + grp;   // the Q column this group holds
-    T xp[RPL], yp[RPL], xq[RPL], yq[RPL];
+    const int q0 = Q * 8 + grp;
+    T xp[RPL], yp[RPL], xq[RPL], yq[VQ ? RPL : 1];
 #pragma unroll
     for (int t = 0; t < RPL; ++t) {
         const int i = gl + 8 * t;
         const bool iok = i < N;
         xp[t] = (pok && iok) ? G[(long long)p * ld + i] : (T)0;
         yp[t] = (pok && iok) ? V[(long long)p * ld + i] : (T)0;
-        xq[t] = (qc < N && iok) ? G[(long long)qc * ld + i] : (T)0;
-        yq[t] = (qc < N && iok) ? V[(long long)qc * ld + i] : (T)0;
+        xq[t] = (q0 < N && iok) ? G[(long long)q0 * ld + i] : (T)0;
+        if constexpr (VQ) yq[t] = (q0 < N && iok) ? V[(long long)q0 * ld + i] : (T)0;
     }
     int big = 0;
     const T tol2 = tol * tol, atol2 = atol * atol;
@@ -763,26 +766,38 @@ __device__ __forceinline__ int cross_block_regs(LP G, LP V, int ld, int N, int P
         be = group_allsum<8>(be);
         ga = group_allsum<8>(ga);
         T cc, ss;
-        if (jacobi_rot<T>(al, be, ga, tol2, atol2, cc, ss)) {
+        if (jacobi_rot<T>(al, be, ga, tol2, atol2, cc, ss)) {   // then both columns are nonzero, so below N
             if (ga * ga > tol * (al * be)) big = 1;
+            const long long qo = (long long)(Q * 8 + ((grp + st) & 7)) * ld;
 #pragma unroll
             for (int t = 0; t < RPL; ++t) {
-                const T a = xp[t], b = xq[t], c = yp[t], d = yq[t];
+                const T a = xp[t], b = xq[t];
                 xp[t] = cc * a - ss * b;
                 xq[t] = ss * a + cc * b;
-                yp[t] = cc * c - ss * d;
-                yq[t] = ss * c + cc * d;
+                if constexpr (VQ) {
+                    const T c = yp[t], d = yq[t];
+                    yp[t] = cc * c - ss * d;
+                    yq[t] = ss * c + cc * d;
+                } else {
+                    const int i = gl + 8 * t;
+                    if (i < N) {
+                        const T c = yp[t], d = V[qo + i];
+                        yp[t] = cc * c - ss * d;
+                        V[qo + i] = ss * c + cc * d;
+                    }
+                }
             }
         }
+        wave_order();
         if (st < 7) {
 #pragma unroll
             for (int t = 0; t < RPL; ++t) {
                 xq[t] = next_group(xq[t]);
-                yq[t] = next_group(yq[t]);
+                if constexpr (VQ) yq[t] = next_group(yq[t]);
             }
         }
     }
-    qc = Q * 8 + ((grp + 7) & 7);
+    const int ql = Q * 8 + ((grp + 7) & 7);
 #pragma unroll
     for (int t = 0; t < RPL; ++t) {
         const int i = gl + 8 * t;
@@ -791,9 +806,9 @@ __device__ __forceinline__ int cross_block_regs(LP G, LP V, int ld, int N, int P
                 G[(long long)p * ld + i] = xp[t];
                 V[(long long)p * ld + i] = yp[t];
             }
-            if (qc < N) {
-                G[(long long)qc * ld + i] = xq[t];
-                V[(long long)qc * ld + i] = yq[t];
+            if (ql < N) {
+                G[(long long)ql * ld + i] = xq[t];
+                if constexpr (VQ) V[(long long)ql * ld + i] = yq[t];
             }
         }
     }
@@ -807,8 +822,8 @@ __device__ __forceinline__ int cross_block_regs(LP G, LP V, int ld, int N, int P
 // rotates columns 8P + g and 8Q + (g + s) mod 8 in step s).  Every column pair meets once per
 // sweep, as in the cyclic order, but only the block rounds end in a workgroup barrier (N / 8 + 1
 // per sweep instead of N - 1): inside a block round the wavefront's own LDS order suffices.
-// Up to N = 32 a cross round keeps its columns in registers (cross_block_regs): faster there;
-// for larger blocks the fixed rows per lane and the register pressure made it slower than LDS.
+// Up to N = 96 a cross round keeps its columns in registers (cross_block_regs): G and V up to
+// N = 32, G alone above; from N = 97 on the LDS steps measured as fast or faster.
 // Returns 1 if some rotation had relative coupling above sqrt(tol).
 template <typename T, int NT, typename LP>
 __device__ __forceinline__ int block_cyclic_sweep(LP G, LP V, int ld, int N, T tol, T atol) {
@@ -833,8 +848,10 @@ __device__ __forceinline__ int block_cyclic_sweep(LP G, LP V, int ld, int N, T t
             int P, Q;
             rr_pair(R, pk, nbp, P, Q);
             if (Q >= nb) continue;
-            if (N <= 32) {
-                big |= cross_block_regs<T, 4>(G, V, ld, N, P, Q, tol, atol);
+            if (N <= 96) {
+                if (N <= 32) big |= cross_block_regs<T, 4, true>(G, V, ld, N, P, Q, tol, atol);
+                else if (N <= 64) big |= cross_block_regs<T, 8, false>(G, V, ld, N, P, Q, tol, atol);
+                else big |= cross_block_regs<T, 12, false>(G, V, ld, N, P, Q, tol, atol);
                 continue;
             }
             for (int st = 0; st < 8; ++st) {
