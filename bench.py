@@ -148,6 +148,39 @@ PER_ITER_CASES = {
 }
 
 
+# Section VII-A, Table I: CDCS-sos CPU seconds (2.8 GHz Core i7, tol 1e-3, at most 2000
+# iterations) for the test POP's order-2 ball relaxation, and its Table III objective values
+TABLE1_CDCS_S = {10: 0.4, 12: 0.7, 14: 1.4, 17: 3.5, 20: 8.5, 24: 22.8, 29: 67.1, 35: 216.9, 42: 686.6}
+TABLE3_CDCS_GAMMA = {10: -9.10, 12: -11.11, 14: -13.12, 17: -16.06, 20: -19.08, 24: -23.15, 29: -28.17,
+                     35: -34.08, 42: -41.05}
+
+
+def table1(ns, tol: float):
+    """The paper's test POP (Section VII-A) at the sizes of Table I, solved in FP64 by sos_solve
+    (the multi-workgroup form from N = 128) at the paper's tolerance; seconds from the solve's
+    own device timing, set-up apart."""
+    from paper_1708_04174_amd import binding as B
+    from sosgen import families as F
+    out = []
+    for n in ns:
+        t0 = time.perf_counter()
+        prob = F.example_pop(n)
+        gen_s = time.perf_counter() - t0
+        w = B.setup_problem(prob, B.sos_default_settings(tol=tol, max_iters=2000))
+        inf = B.sos_solve(w)
+        x, _, _ = B.sos_get_solution(w) if inf["tau"] > 0 else (np.full(1, np.nan), None, None)
+        w.free()
+        rec = {"n": n, "N": max(prob.psd_dims), "m": prob.m, "status": inf["status_name"], "iters": inf["iters"],
+               "gamma": float(x[0]), "solve_s": inf["solve_ms"] / 1e3, "setup_s": inf["setup_ms"] / 1e3,
+               "ms_per_iter": inf["solve_ms"] / max(inf["iters"], 1), "sweeps": inf["eig_sweeps"],
+               "generate_s": gen_s, "paper_cdcs_s": TABLE1_CDCS_S.get(n), "paper_cdcs_gamma": TABLE3_CDCS_GAMMA.get(n)}
+        log(f"[table1] n {n}: N {rec['N']}, m {rec['m']}: {rec['status']} in {rec['iters']} iterations, "
+            f"gamma {rec['gamma']:.4f}, {rec['solve_s']:.2f} s ({rec['ms_per_iter']:.2f} ms/iter; paper's CDCS-sos "
+            f"{rec['paper_cdcs_s']} s, gamma {rec['paper_cdcs_gamma']})")
+        out.append(rec)
+    return out
+
+
 def per_iteration(cases, warm_iters: int, timed_iters: int):
     """ms per iteration of sos_step on single problems (one workgroup), after warm_iters
     iterations (warm Jacobi starts settled), in both precision forms, with the device-clock
@@ -250,6 +283,9 @@ def main():
     ap.add_argument("--per-iter", nargs="*", default=None, metavar="CASE",
                     help="only time sos_step per iteration on single problems (cases: "
                          + ", ".join(PER_ITER_CASES) + "; none given: all) and print them as one JSON line")
+    ap.add_argument("--table1", nargs="*", type=int, default=None, metavar="N",
+                    help="only solve the paper's test POP at these n (default: Table I's sizes) in FP64 at "
+                         "--tol (use 1e-3, the paper's) and print one JSON line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 256 MiB device buffer three times (the known-size kernel that "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -270,6 +306,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": COPY_PROBE_BYTES, "copies": 3}), flush=True)
+        return
+    if args.table1 is not None:
+        print(json.dumps({"table1": table1(args.table1 or sorted(TABLE1_CDCS_S), args.tol), "tol": args.tol}),
+              flush=True)
         return
     if args.per_iter is not None:
         cases = args.per_iter or list(PER_ITER_CASES)
