@@ -10,6 +10,8 @@ in graded monomial order, and returns a ConicProblem.
 * example_pop        - the quartic test POP of Section VII-A on the unit ball.
 * lyapunov           - global Lyapunov search for a cubic vector field
                        (Section II-B, the Lyapunov SOS program) with a quartic V.
+* lyapunov_local     - local stability on a ball with a quadratic V and a quadratic
+                       multiplier (Section VII-B, Table II's programs).
 * small closed forms - univariate, bivariate, separable, infeasible and unbounded
                        programs whose answers are known without any solver.
 """
@@ -244,6 +246,76 @@ def lyapunov_features(seed: int, n: int = 6) -> np.ndarray:
     quad = monomials(n, 2, min_degree=2)
     coef = rng.standard_normal((n, len(quad)))
     return np.concatenate([[sigma], (sigma * coef).reshape(-1)])
+
+
+# ---------------------------------------------------------------- local Lyapunov family (Table II)
+def local_field(n: int, rng: np.random.Generator, terms: int = 2, scale: float = 1.0):
+    """A cubic vector field with a linearly stable equilibrium at the origin (Section VII-B):
+    f(x) = J x + (per component) `terms` random quadratic and `terms` random cubic monomials with
+    N(0, scale^2) coefficients, J = -I + N(0, 1/(4n)) entries, redrawn until every eigenvalue of J
+    has real part below -0.1.  Returns (J, f)."""
+    while True:
+        J = -np.eye(n) + rng.standard_normal((n, n)) * (0.5 / np.sqrt(n))
+        if np.max(np.linalg.eigvals(J).real) < -0.1:
+            break
+    quad = monomials(n, 2, min_degree=2)
+    cub = monomials(n, 3, min_degree=3)
+    f = []
+    for i in range(n):
+        fi = Poly(n)
+        for j in range(n):
+            fi = fi + Poly.var(n, j).scale(J[i, j])
+        for pool in (quad, cub):
+            for k in rng.choice(len(pool), size=min(terms, len(pool)), replace=False):
+                fi = fi + Poly.mono(pool[k], scale * float(rng.standard_normal()))
+        f.append(fi)
+    return J, f
+
+
+def local_lyapunov_from_field(n: int, f: Sequence[Poly], radius2: float = 0.1, eps: float = 1.0,
+                              meta: Optional[dict] = None) -> ConicProblem:
+    """Local stability on the ball D = {x : radius2 - |x|^2 >= 0} with a quadratic Lyapunov function
+    (Section II-B's Lyapunov conditions, Section VII-B's experiment): find V = x^T Q x and a
+    quadratic multiplier s with
+
+        V - eps |x|^2                        SOS   (Gram basis x_1..x_n),
+        s                                    SOS   (Gram basis x_1..x_n),
+        -grad V . f - eps |x|^2 - s (radius2 - |x|^2)   SOS   (Gram basis: monomials of degree 1..2),
+
+    so that V > 0 and dV/dt < 0 on D away from the origin.  The coefficients of V and of s are the
+    free variables (the multiplier enters as an extra polynomial, Section II-B), t = n (n + 1); rows
+    match the coefficients that can occur: degree 2 for the first two identities, degrees 2..4 for
+    the third.  Sizes: N = C(n+2, 2) - 1, m = C(n+4, 4) + n^2 - 1, as in Table II.  Feasibility
+    problem (c = 0)."""
+    quad = monomials(n, 2, min_degree=2)
+    nq = len(quad)
+    t = 2 * nq
+    neg_sq = -_sum_sq(n, eps)
+    ball = Poly.const(n, radius2) - _sum_sq(n)
+    g1 = {i: Poly.mono(e, -1.0) for i, e in enumerate(quad)}
+    g2 = {nq + i: Poly.mono(e, -1.0) for i, e in enumerate(quad)}
+    g3 = {}
+    for i, e in enumerate(quad):
+        mono = Poly.mono(e)
+        acc = Poly(n)
+        for k in range(n):
+            acc = acc + mono.diff(k) * f[k]
+        g3[i] = acc                                  # -u_i * (grad x^e . f) on the left side
+        g3[nq + i] = mono * ball                     # -w_i * x^e (radius2 - |x|^2)
+    one = Poly.const(n, 1.0)
+    eq1 = SOSEquation(row_degree=2, row_min_degree=2, g0=neg_sq, g=g1, blocks=[(1, one, 1)])
+    eq2 = SOSEquation(row_degree=2, row_min_degree=2, g0=Poly(n), g=g2, blocks=[(1, one, 1)])
+    eq3 = SOSEquation(row_degree=4, row_min_degree=2, g0=neg_sq, g=g3, blocks=[(2, one, 1)])
+    md = {"kind": "lyapunov_local", "n_vars": n, "eps": eps, "radius2": radius2, "v_monomials": nq}
+    md.update(meta or {})
+    return build_sos_sdp(n, t, np.zeros(t), [eq1, eq2, eq3], md)
+
+
+def lyapunov_local(n: int, seed: int, terms: int = 2, scale: float = 1.0) -> ConicProblem:
+    """Table II's program for a random cubic system with n states (local_field)."""
+    rng = np.random.default_rng(seed)
+    J, f = local_field(n, rng, terms, scale)
+    return local_lyapunov_from_field(n, f, meta={"family": "lyapunov_local", "seed": seed, "J": J, "f": f})
 
 
 # ---------------------------------------------------------------- closed-form cases

@@ -31,11 +31,17 @@ from .poly import Poly, monomials
 
 @dataclass
 class SOSEquation:
-    """One polynomial identity g0 - sum_i u_i g[i] = sum_b weight_b * (Gram form of degree 2*half_deg_b)."""
+    """One polynomial identity g0 - sum_i u_i g[i] = sum_b weight_b * (Gram form of degree 2*half_deg_b).
+
+    Rows are the monomials of degree row_min_degree..row_degree; a block is (half_degree, weight)
+    with the Gram basis of all monomials of degree <= half_degree, or (half_degree, weight,
+    min_degree) with the basis of degrees min_degree..half_degree (e.g. a form without constant
+    or linear terms, as in the local Lyapunov conditions)."""
     row_degree: int                    # rows = monomials of degree <= row_degree
     g0: Poly
     g: Dict[int, Poly]                 # free-variable index -> polynomial g_i (sparse over i)
-    blocks: List[tuple]                # (half_degree, weight Poly) per Gram block
+    blocks: List[tuple]                # (half_degree, weight Poly[, min_degree]) per Gram block
+    row_min_degree: int = 0
 
 
 @dataclass
@@ -82,8 +88,8 @@ def build_sos_sdp(n: int, n_free: int, w: Sequence[float], equations: Sequence[S
     block_cols = []
     for eq in equations:
         offs = []
-        for half_deg, _wt in eq.blocks:
-            N = len(monomials(n, half_deg))
+        for blk in eq.blocks:
+            N = len(monomials(n, blk[0], blk[2] if len(blk) > 2 else 0))
             offs.append(col)
             psd_dims.append(N)
             col += N * N
@@ -92,14 +98,14 @@ def build_sos_sdp(n: int, n_free: int, w: Sequence[float], equations: Sequence[S
 
     row0 = 0
     for eq, offs in zip(equations, block_cols):
-        row_basis = monomials(n, eq.row_degree)
+        row_basis = monomials(n, eq.row_degree, eq.row_min_degree)
         row_of = {e: k for k, e in enumerate(row_basis)}
         m_eq = len(row_basis)
 
         def row_index(e) -> int:
             r = row_of.get(tuple(e))
             if r is None:
-                raise ValueError(f"monomial {e} exceeds the row degree {eq.row_degree}")
+                raise ValueError(f"monomial {e} is outside the row degrees {eq.row_min_degree}..{eq.row_degree}")
             return r
 
         # right-hand side b_alpha = g_{0,alpha}
@@ -118,8 +124,9 @@ def build_sos_sdp(n: int, n_free: int, w: Sequence[float], equations: Sequence[S
                 vals.append(np.array([cf]))
 
         # Gram blocks: entry (r, s) of X_b meets monomial v_r + v_s + delta of the weight
-        for (half_deg, wt), off in zip(eq.blocks, offs):
-            basis = np.array(monomials(n, half_deg), dtype=np.int64).reshape(-1, n)
+        for blk, off in zip(eq.blocks, offs):
+            half_deg, wt = blk[0], blk[1]
+            basis = np.array(monomials(n, half_deg, blk[2] if len(blk) > 2 else 0), dtype=np.int64).reshape(-1, n)
             N = basis.shape[0]
             pair = basis[:, None, :] + basis[None, :, :]          # (N, N, n): exponent of v_r v_s
             rr, ss = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
