@@ -173,10 +173,47 @@ def table1(ns, tol: float):
         rec = {"n": n, "N": max(prob.psd_dims), "m": prob.m, "status": inf["status_name"], "iters": inf["iters"],
                "gamma": float(x[0]), "solve_s": inf["solve_ms"] / 1e3, "setup_s": inf["setup_ms"] / 1e3,
                "ms_per_iter": inf["solve_ms"] / max(inf["iters"], 1), "sweeps": inf["eig_sweeps"],
+               "affine_ms_per_iter": inf["affine_ms"] / max(inf["iters"], 1),
+               "projection_ms_per_iter": inf["eig_ms"] / max(inf["iters"], 1), "residual_ms": inf["resid_ms"],
                "generate_s": gen_s, "paper_cdcs_s": TABLE1_CDCS_S.get(n), "paper_cdcs_gamma": TABLE3_CDCS_GAMMA.get(n)}
         log(f"[table1] n {n}: N {rec['N']}, m {rec['m']}: {rec['status']} in {rec['iters']} iterations, "
             f"gamma {rec['gamma']:.4f}, {rec['solve_s']:.2f} s ({rec['ms_per_iter']:.2f} ms/iter; paper's CDCS-sos "
             f"{rec['paper_cdcs_s']} s, gamma {rec['paper_cdcs_gamma']})")
+        out.append(rec)
+    return out
+
+
+# Section VII-B, Table II: sizes (N, m, t) and CDCS-sos CPU seconds (same machine and settings as
+# Table I) for the local Lyapunov programs of random cubic systems
+TABLE2 = {10: (65, 1100, 110, 0.3), 12: (90, 1963, 156, 0.4), 14: (119, 3255, 210, 0.6), 17: (170, 6273, 306, 1.1),
+          20: (230, 11025, 420, 2.4), 24: (324, 21050, 600, 5.1), 29: (464, 41760, 870, 14.3),
+          35: (665, 83475, 1260, 37.4), 42: (945, 164948, 1806, 92.8)}
+
+
+def table2(ns, tol: float, seed: int = 0):
+    """Table II's programs (sosgen.families.lyapunov_local, one random system per n) solved in FP64
+    by sos_solve at the paper's tolerance; seconds from the solve's device timing, set-up apart."""
+    from paper_1708_04174_amd import binding as B
+    from sosgen import families as F
+    out = []
+    for n in ns:
+        t0 = time.perf_counter()
+        prob = F.lyapunov_local(n, seed)
+        gen_s = time.perf_counter() - t0
+        w = B.setup_problem(prob, B.sos_default_settings(tol=tol, max_iters=2000))
+        inf = B.sos_solve(w)
+        w.free()
+        paper = TABLE2.get(n)
+        rec = {"n": n, "N": max(prob.psd_dims), "m": prob.m, "t": prob.n_free, "status": inf["status_name"],
+               "iters": inf["iters"], "solve_s": inf["solve_ms"] / 1e3, "setup_s": inf["setup_ms"] / 1e3,
+               "ms_per_iter": inf["solve_ms"] / max(inf["iters"], 1), "sweeps": inf["eig_sweeps"],
+               "affine_ms_per_iter": inf["affine_ms"] / max(inf["iters"], 1),
+               "projection_ms_per_iter": inf["eig_ms"] / max(inf["iters"], 1), "residual_ms": inf["resid_ms"],
+               "generate_s": gen_s, "paper_N_m_t": paper[:3] if paper else None,
+               "paper_cdcs_s": paper[3] if paper else None}
+        log(f"[table2] n {n}: N {rec['N']}, m {rec['m']}, t {rec['t']}: {rec['status']} in {rec['iters']} "
+            f"iterations, {rec['solve_s']:.2f} s ({rec['ms_per_iter']:.2f} ms/iter); paper's sizes "
+            f"{rec['paper_N_m_t']}, CDCS-sos {rec['paper_cdcs_s']} s")
         out.append(rec)
     return out
 
@@ -283,6 +320,9 @@ def main():
     ap.add_argument("--per-iter", nargs="*", default=None, metavar="CASE",
                     help="only time sos_step per iteration on single problems (cases: "
                          + ", ".join(PER_ITER_CASES) + "; none given: all) and print them as one JSON line")
+    ap.add_argument("--table2", nargs="*", type=int, default=None, metavar="N",
+                    help="only solve Table II's local Lyapunov programs at these n (default: Table II's sizes) "
+                         "in FP64 at --tol and print them as one JSON line")
     ap.add_argument("--table1", nargs="*", type=int, default=None, metavar="N",
                     help="only solve the paper's test POP at these n (default: Table I's sizes) in FP64 at "
                          "--tol (use 1e-3, the paper's) and print one JSON line")
@@ -306,6 +346,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": COPY_PROBE_BYTES, "copies": 3}), flush=True)
+        return
+    if args.table2 is not None:
+        print(json.dumps({"table2": table2(args.table2 or sorted(TABLE2), args.tol), "tol": args.tol}), flush=True)
         return
     if args.table1 is not None:
         print(json.dumps({"table1": table1(args.table1 or sorted(TABLE1_CDCS_S), args.tol), "tol": args.tol}),

@@ -643,7 +643,9 @@ void setup_coop(sos_work *w) {
     w->coop_bcols = bcols;
     w->coop_threads = thr;
     const size_t nm = (size_t)w->nmax;
-    w->d_coop_scr = w->mem.alloc<double>(3 * nm * nm + nm + SOS_COOP_MAX_WG);
+    // G, V, W, sigma, two partial sums per workgroup, the affine step's two k-vectors
+    const size_t kp = ((size_t)w->k + 63) & ~(size_t)63;
+    w->d_coop_scr = w->mem.alloc<double>(3 * nm * nm + nm + 2 * SOS_COOP_MAX_WG + 2 * kp);
     w->d_ctl = w->mem.alloc<CoopCtl>(1);
     if (!w->d_coop_scr || !w->d_ctl) throw Status(SOS_E_NOMEM, "hipMalloc failed");
     w->use_coop = true;

@@ -1852,6 +1852,197 @@ __device__ __noinline__ void coop_project_block(T *__restrict__ vs, T *__restric
     grid_sync(ctl);
 }
 
+// The affine step (Section IV-A, the projection onto the embedding's subspace, with the
+// inverse of Section IV-B) of one FP64 problem spread over the cooperative grid: the same phases
+// and per-row arithmetic as affine_phase, each phase over all workgroups with a grid barrier
+// after it.  A^T_f x and S^{-1} (A^T_f x) live in global scratch (kq, kz, k entries each); the
+// product with S^{-1} takes whole rows per wavefront (S^{-1} is symmetric, so a row is a
+// contiguous column), each workgroup always the same rows; the two inner products that give
+// theta are summed in workgroup order (parts, two per workgroup), so every workgroup computes the
+// same theta.  Ends without a barrier: the caller's next grid barrier publishes u, v and tau.
+template <int NT>
+__device__ __noinline__ void coop_affine_phase(const ProbDesc &P, const RunParams &rp, double *__restrict__ wy,
+                                               double *__restrict__ wx, double *__restrict__ kq,
+                                               double *__restrict__ kz, double *parts, CoopCtl *ctl,
+                                               double *s_red) {
+    typedef double T;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr int NW = NT / 64;
+    const int wg = blockIdx.x, nwg = gridDim.x;
+    const long long gt = (long long)wg * NT + tid, gstride = (long long)nwg * NT;
+    const long long ggrp = gt >> 3, ngrp = gstride >> 3;
+    const int gw = wg * NW + wid, ngw = nwg * NW;
+    const int m = P.m, nx = P.nx, k = P.k, nfree = P.nfree;
+    T *__restrict__ u = P.u64;
+    T *__restrict__ v = P.v64;
+    const T *__restrict__ val = P.val64;
+    const T *__restrict__ colval = P.colval64;
+    const T *__restrict__ fval = P.fval64;
+    const T *__restrict__ frval = P.frval64;
+    const T *__restrict__ dinv = P.dinv64;
+    const T *__restrict__ h = P.h64;
+    const T *__restrict__ b = P.b64;
+    const T *__restrict__ c = P.c64;
+    const T *__restrict__ cw = P.cw64;
+    const int *__restrict__ rowptr = P.rowptr;
+    const int *__restrict__ colidx = P.colidx;
+    const int *__restrict__ colrow = P.colrow;
+    const double tau = P.tk[0], kap = P.tk[1];
+    const double wt = tau + kap;
+    const T *__restrict__ uy = u + nx;
+    const int gl = tid & 7;
+
+    // P1: x = (w2 - A w1) / d, rows over the grid
+    for (long long a = gt; a < m; a += gstride) {
+        T acc = uy[a] + b[a] * wt;
+        T acc1 = 0, acc2 = 0, acc3 = 0;
+        const int e1 = rowptr[a + 1];
+        int e = rowptr[a];
+        for (; e + 4 <= e1; e += 4) {
+            const int j0 = colidx[e], j1 = colidx[e + 1], j2 = colidx[e + 2], j3 = colidx[e + 3];
+            acc -= val[e] * (u[j0] + v[j0] - c[j0] * wt);
+            acc1 -= val[e + 1] * (u[j1] + v[j1] - c[j1] * wt);
+            acc2 -= val[e + 2] * (u[j2] + v[j2] - c[j2] * wt);
+            acc3 -= val[e + 3] * (u[j3] + v[j3] - c[j3] * wt);
+        }
+        for (; e < e1; ++e) {
+            const int j = colidx[e];
+            acc -= val[e] * (u[j] + v[j] - c[j] * wt);
+        }
+        wy[a] = (acc + acc1 + (acc2 + acc3)) * dinv[a];
+    }
+    grid_sync(ctl);
+
+    if (k > 0) {
+        // P2: q = A_f^T x (a group of 8 lanes per column), then z = S^{-1} q (a wavefront per row)
+        const int *__restrict__ fptr = P.fptr;
+        const int *__restrict__ frow = P.frow;
+        for (long long j = ggrp; j < k; j += ngrp) {
+            double s = 0.0;
+            const int e1 = fptr[j + 1];
+            for (int e = fptr[j] + gl; e < e1; e += 8) s += fval[e] * wy[frow[e]];
+            s = group_allsum<8>(s);
+            if (gl == 0) kq[j] = s;
+        }
+        grid_sync(ctl);
+        const double *__restrict__ Sinv = P.Sinv;
+        for (int i = gw; i < k; i += ngw) {
+            const double *__restrict__ row = Sinv + (long long)i * k;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int j = lane;
+            for (; j + 192 < k; j += 256) {
+                a0 += row[j] * kq[j];
+                a1 += row[j + 64] * kq[j + 64];
+                a2 += row[j + 128] * kq[j + 128];
+                a3 += row[j + 192] * kq[j + 192];
+            }
+            for (; j < k; j += 64) a0 += row[j] * kq[j];
+            const double t = wave_allsum((a0 + a1) + (a2 + a3));
+            if (lane == 0) kz[i] = t;
+        }
+        grid_sync(ctl);
+    }
+
+    // P3: sigma_2 = x - D^{-1} A_f z ; partial b^T sigma_2
+    double bs = 0.0;
+    {
+        const int *__restrict__ frptr = P.frptr;
+        const int *__restrict__ frcol = P.frcol;
+        for (long long a = gt; a < m; a += gstride) {
+            T s2 = wy[a];
+            if (k > 0) {
+                double acc = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+                const int e1 = frptr[a + 1];
+                int e = frptr[a];
+                for (; e + 4 <= e1; e += 4) {
+                    acc += frval[e] * kz[frcol[e]];
+                    acc1 += frval[e + 1] * kz[frcol[e + 1]];
+                    acc2 += frval[e + 2] * kz[frcol[e + 2]];
+                    acc3 += frval[e + 3] * kz[frcol[e + 3]];
+                }
+                for (; e < e1; ++e) acc += frval[e] * kz[frcol[e]];
+                s2 = s2 - ((acc + acc1) + (acc2 + acc3)) * dinv[a];
+            }
+            wy[a] = s2;
+            bs += b[a] * s2;
+        }
+    }
+    grid_sync(ctl);
+
+    // P4: sigma_1 = w1 + A^T sigma_2 ; partial c^T sigma_1
+    double cs = 0.0;
+    {
+        for (long long e = gt; e < nx; e += gstride) {
+            const int r = colrow[e];
+            if (r <= -2) continue;
+            const T w1 = u[e] + v[e] - c[e] * wt;
+            const T s1 = r >= 0 ? w1 + colval[e] * wy[r] : w1;
+            wx[e] = s1;
+            cs += cw[e] * s1;
+        }
+        const int *__restrict__ fptr = P.fptr;
+        const int *__restrict__ frow = P.frow;
+        const int *__restrict__ fcol = P.fcol;
+        for (long long j = ggrp; j < k; j += ngrp) {
+            T acc = 0;
+            const int i1 = fptr[j + 1];
+            for (int i = fptr[j] + gl; i < i1; i += 8) acc += fval[i] * wy[frow[i]];
+            acc = group_allsum<8>(acc);
+            if (gl == 0) {
+                const int e = fcol[j];
+                const T s1 = u[e] + v[e] - c[e] * wt + acc;
+                wx[e] = s1;
+                cs += cw[e] * s1;
+            }
+        }
+    }
+    block_sum2<NT>(cs, bs, s_red);
+    if (tid == 0) {
+        parts[2 * wg] = cs;
+        parts[2 * wg + 1] = bs;
+    }
+    grid_sync(ctl);
+    if (tid == 0) {
+        double tc = 0.0, tb = 0.0;
+        for (int g = 0; g < nwg; ++g) {
+            tc += __hip_atomic_load(&parts[2 * g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tb += __hip_atomic_load(&parts[2 * g + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_red[0] = tc;
+        s_red[1] = tb;
+    }
+    __syncthreads();
+    const double theta = (s_red[0] - s_red[1]) / P.eta;
+    const double al = rp.alpha;
+    const bool relax = rp.alpha != 1.0;
+
+    // P5: u_hat, w = u_hat - v, direct updates of the free, y and tau parts
+    for (long long e = gt; e < nx; e += gstride) {
+        T uh = wx[e] - theta * h[e];
+        if (relax) uh = al * uh + (1.0 - al) * u[e];
+        const T w = uh - v[e];
+        if (e < nfree) {
+            u[e] = w;
+            v[e] = 0.0;
+        } else {
+            v[e] = w;
+        }
+    }
+    for (long long a = gt; a < m; a += gstride) {
+        T uh = wy[a] - theta * h[nx + a];
+        if (relax) uh = al * uh + (1.0 - al) * u[nx + a];
+        u[nx + a] = uh;
+    }
+    if (wg == 0 && tid == 0) {
+        double uht = wt + theta;
+        if (relax) uht = al * uht + (1.0 - al) * tau;
+        const double wtt = uht - kap;
+        const double tn = wtt > 0.0 ? wtt : 0.0;
+        P.tk[0] = tn;
+        P.tk[1] = tn - wtt;
+    }
+}
+
 // Whole FP64 iterations of one problem over a cooperative grid (see sos_launch_admm_coop).
 template <int NT>
 __global__ __launch_bounds__(NT) void admm_coop(RunParams rp, CoopCtl *ctl, double *scr, int bcols) {
@@ -1864,10 +2055,10 @@ __global__ __launch_bounds__(NT) void admm_coop(RunParams rp, CoopCtl *ctl, doub
     const int wg = blockIdx.x, tid = threadIdx.x;
     const int nm = P.nmax;
     T *G = scr, *V = G + (long long)nm * nm, *W = V + (long long)nm * nm, *sig = W + (long long)nm * nm;
-    double *parts = sig + nm;
+    double *parts = sig + nm;                            // 2 per workgroup
+    double *kq = parts + 2 * SOS_COOP_MAX_WG, *kz = kq + ((P.k + 63) & ~63);
     T *wy = reinterpret_cast<T *>(rp.work);
     T *wx = wy + ((P.m + 63) & ~63);
-    double *s_z = reinterpret_cast<double *>(dyn_lds);
     T *u = P.u64, *v = P.v64, *vstore = P.vs64;
     bool warm = P.tk[2] != 0.0;
     if (tid == 0) s_sweeps = 0;
@@ -1876,7 +2067,7 @@ __global__ __launch_bounds__(NT) void admm_coop(RunParams rp, CoopCtl *ctl, doub
     const int cap = rp.iters;
     while (it < cap) {
         const unsigned long long t0 = wall_clock64();
-        if (wg == 0) affine_phase<T, NT, T>(P, rp, wy, wx, s_z, s_red);
+        coop_affine_phase<NT>(P, rp, wy, wx, kq, kz, parts, ctl, s_red);
         grid_sync(ctl);
         const unsigned long long t1 = wall_clock64();
         t_aff += t1 - t0;
@@ -2326,10 +2517,10 @@ int sos_static_scratch(void **ptr) {
 
 // dynamic LDS of a cooperative launch: the affine step's k-vector and partial sums, or the
 // Jacobi blocks' columns of G and V (the two phases are separated by barriers)
+// dynamic LDS of admm_coop: two column blocks of G and V (the affine step keeps its k-vectors in
+// global scratch)
 static size_t coop_lds_bytes(const RunParams &rp, int bcols) {
-    const size_t jac = sizeof(double) * 4 * (size_t)bcols * rp.eig_ld;
-    const size_t aff = sizeof(double) * 2 * SOS_KMAX_LDS;
-    return jac > aff ? jac : aff;
+    return sizeof(double) * 4 * (size_t)bcols * rp.eig_ld;
 }
 
 int sos_coop_max_grid(int threads, const RunParams &rp, int bcols) {
