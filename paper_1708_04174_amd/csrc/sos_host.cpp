@@ -38,7 +38,8 @@ constexpr int kLanesPerPair[7] = {16, 16, 8, 8, 16, 16, 16};
 // FP64 single solves take the multi-workgroup (cooperative) path from this largest block size on
 // (eig_form 0); eig_form 3 takes it for every block
 constexpr int kCoopNmin = 128;
-// columns per Jacobi block of the multi-workgroup eigensolver (fewer when LDS is short)
+// columns per Jacobi block of the multi-workgroup eigensolver (a pair of blocks is one 16-wide
+// matrix-core tile)
 constexpr int kCoopBcols = 8;
 // the lane-group form's sweep order when G and V sit in LDS: 8 = block-cyclic, 0 = cyclic
 constexpr int kJacBlock = 8;
@@ -119,7 +120,7 @@ struct sos_work {
     bool active64 = true;     // which copy of (u, v) holds the current iterate
     // multi-workgroup path (FP64 single solves with a large block): cooperative grid, scratch
     bool use_coop = false;
-    int coop_grid = 0, coop_bcols = 0, coop_threads = 512;
+    int coop_grid = 0, coop_threads = 512;
     double *d_coop_scr = nullptr;
     CoopCtl *d_ctl = nullptr;
     // equilibration: the iteration runs on D A E; x = E x^, y = D y^, z = z^ / E
@@ -622,25 +623,22 @@ void build(sos_work *w, const sos_csc *A, const double *b, const double *c, cons
 RunParams single_params(sos_work *w, int mode, int iters, int min_iters, double tol);
 
 // Multi-workgroup path: FP64, a block of at least kCoopNmin (eig_form 0) or any (eig_form 3), a
-// device with cooperative launches.  Column blocks of up to kCoopBcols columns, as many as LDS
-// holds (two blocks of G and V, FP64); one workgroup per pair of blocks.
+// device with cooperative launches.  Column blocks of kCoopBcols columns; one workgroup per pair
+// of blocks, up to what the device holds at once.
 void setup_coop(sos_work *w) {
     w->use_coop = false;
     if (w->st.precision != SOS_FP64 || w->N.empty()) return;
     if (!(w->st.eig_form == 3 || (w->st.eig_form == 0 && w->nmax >= kCoopNmin))) return;
     const int thr = (w->threads == 256 || w->threads == 512) ? w->threads : 512;
     RunParams rp = single_params(w, RUN_STEP, 0, 0, w->st.tol);
-    int bcols = kCoopBcols;
-    while (bcols > 1 && (long long)sizeof(double) * 4 * bcols * w->nmax > kLdsBudget) --bcols;
-    const int gmax = sos_coop_max_grid(thr, rp, bcols);
+    const int gmax = sos_coop_max_grid(thr, rp);
     if (gmax < 1) {
         if (w->st.eig_form == 3) throw Status(SOS_E_INVAL, "multi-workgroup eigensolver unavailable on this device/shape");
         return;
     }
-    const int nb = (w->nmax + bcols - 1) / bcols;
+    const int nb = (w->nmax + kCoopBcols - 1) / kCoopBcols;
     const int pairs = (nb + (nb & 1)) / 2;
     w->coop_grid = std::max(1, std::min(gmax, pairs));
-    w->coop_bcols = bcols;
     w->coop_threads = thr;
     const size_t nm = (size_t)w->nmax;
     // G, V, W, sigma, two partial sums per workgroup, the affine step's two k-vectors
@@ -653,7 +651,7 @@ void setup_coop(sos_work *w) {
 
 // the FP64 iterations of a single solve over the cooperative grid; checks the barrier's flag
 void run_coop(sos_work *w, const RunParams &rp) {
-    if (sos_launch_admm_coop(w->coop_threads, w->coop_grid, rp, w->d_ctl, w->d_coop_scr, w->coop_bcols, w->stream))
+    if (sos_launch_admm_coop(w->coop_threads, w->coop_grid, rp, w->d_ctl, w->d_coop_scr, w->stream))
         throw Status(SOS_E_HIP, std::string("cooperative launch failed: ") + sos_launch_message());
     CoopCtl c;
     hip_check(hipMemcpyAsync(&c, w->d_ctl, sizeof(c), hipMemcpyDeviceToHost, w->stream), "copy");
@@ -755,7 +753,7 @@ void step_impl(sos_work *w, int32_t iters, sos_info *info, bool static_scratch) 
     set_active(w, fp64);
     hip_check(hipEventRecord(w->ev0, w->stream), "event");
     if (fp64 && w->use_coop && !static_scratch) {
-        if (sos_launch_admm_coop(w->coop_threads, w->coop_grid, rp, w->d_ctl, w->d_coop_scr, w->coop_bcols, w->stream))
+        if (sos_launch_admm_coop(w->coop_threads, w->coop_grid, rp, w->d_ctl, w->d_coop_scr, w->stream))
             throw Status(SOS_E_HIP, std::string("cooperative launch failed: ") + sos_launch_message());
     } else {
         run_single(w, fp64, rp);

@@ -145,14 +145,14 @@ int sos_launch_reset_state(const ProbDesc *probs_dev, int count, int max_len, vo
 int sos_launch_warm_start(int fp64, int threads, int grid, const RunParams &rp, const float *pred, long long ld,
                           void *stream);
 // Multi-workgroup FP64 solve of problem 0 of rp (one cooperative launch of `grid` workgroups):
-// workgroup 0 runs the affine step and the residual checks, every workgroup the block Jacobi
-// eigensolver (column blocks of bcols columns) and the MFMA products.  scratch: 3 nmax^2 + nmax
-// doubles (G, V, W, sigma) + SOS_COOP_MAX_WG doubles of partial sums.  ctl: zeroed by the launcher.
-// Returns 0, -1 (unsupported shape), -4 (launch failed).
-int sos_launch_admm_coop(int threads, int grid, const RunParams &rp, CoopCtl *ctl, double *scratch, int bcols,
-                         void *stream);
+// every workgroup takes part in the affine step, the block Jacobi eigensolver (column blocks of 8,
+// a pair of blocks per workgroup and block round) and the MFMA products; workgroup 0 runs the
+// residual checks.  scratch: 3 nmax^2 + nmax doubles (G, V, W, sigma), 2 SOS_COOP_MAX_WG doubles
+// of partial sums, 2 x (k rounded up to 64) doubles for the affine step.  ctl: zeroed by the
+// launcher.  Returns 0, -1 (unsupported shape), -4 (launch failed).
+int sos_launch_admm_coop(int threads, int grid, const RunParams &rp, CoopCtl *ctl, double *scratch, void *stream);
 // Largest grid a cooperative launch of the given width may use on this device (0 if unsupported).
-int sos_coop_max_grid(int threads, const RunParams &rp, int bcols);
+int sos_coop_max_grid(int threads, const RunParams &rp);
 // Device address of the static scratch (SOS_STATIC_SCRATCH_BYTES) on the current device,
 // looked up once per device; 0 on success, -4 if the lookup failed.
 int sos_static_scratch(void **ptr);

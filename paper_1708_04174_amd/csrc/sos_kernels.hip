@@ -1734,18 +1734,206 @@ __device__ __forceinline__ int wave_rotate_pair(typename Lds<T>::type *gp, typen
     return ga * ga > tol * (al * be) ? 2 : 1;
 }
 
+// Dynamic LDS of gram_block_round for NT threads: NT / 64 partial Gram tiles, the Gram matrix C,
+// its eigenvectors Z (16 x 16 each), the rotations of one round and two flags.
+__host__ __device__ constexpr size_t gram_round_lds_bytes(int nt) {
+    return sizeof(double) * ((size_t)(nt / 64) * 256 + 2 * 256 + 2 * 8) + sizeof(int) * (8 + 2);
+}
+
+// One cyclic sweep of two-sided Jacobi on the 16 x 16 symmetric C (row-major, LDS) by one
+// wavefront, accumulating the rotations in Z (set to I here): round-robin order, 8 disjoint
+// rotations per round (rows, then columns of C, then columns of Z).  Since C = G_b^T G_b, rotating C
+// on both sides by the rotation of columns p, q is that column rotation seen through the Gram
+// matrix: the sweep is the one-sided sweep over the 16 columns, done on 16 x 16 numbers instead of
+// on N-long columns.  A pair is rotated by jacobi_rot (same thresholds and angle as a column pair
+// of the one-sided form).
+__device__ __forceinline__ void small_jacobi16(double *C, double *Z, double *rc, double *rs, int *rpq, double tol2,
+                                               double atol2) {
+    const int lane = threadIdx.x & 63;
+    for (int e = lane; e < 256; e += 64) Z[e] = (e >> 4) == (e & 15) ? 1.0 : 0.0;
+    wave_order();
+    {
+        for (int r = 0; r < 15; ++r) {
+            if (lane < 8) {
+                int p, q;
+                rr_pair(r, lane, 16, p, q);
+                double c = 1.0, sn = 0.0;
+                if (!jacobi_rot<double>(C[p * 16 + p], C[q * 16 + q], C[p * 16 + q], tol2, atol2, c, sn)) {
+                    c = 1.0;
+                    sn = 0.0;
+                }
+                rc[lane] = c;
+                rs[lane] = sn;
+                rpq[lane] = p | (q << 8);
+            }
+            wave_order();
+            if (!__any(lane < 8 && rs[lane & 7] != 0.0)) continue;
+            for (int task = lane; task < 128; task += 64) {   // rows p, q of C: J^T C
+                const int k = task >> 4, j = task & 15;
+                const double sn = rs[k];
+                if (sn != 0.0) {
+                    const int p = rpq[k] & 255, q = rpq[k] >> 8;
+                    const double c = rc[k], x = C[p * 16 + j], y = C[q * 16 + j];
+                    C[p * 16 + j] = c * x - sn * y;
+                    C[q * 16 + j] = sn * x + c * y;
+                }
+            }
+            wave_order();
+            for (int task = lane; task < 128; task += 64) {   // columns p, q of C and Z: C J, Z J
+                const int k = task >> 4, i = task & 15;
+                const double sn = rs[k];
+                if (sn != 0.0) {
+                    const int p = rpq[k] & 255, q = rpq[k] >> 8;
+                    const double c = rc[k];
+                    const double x = C[i * 16 + p], y = C[i * 16 + q];
+                    C[i * 16 + p] = c * x - sn * y;
+                    C[i * 16 + q] = sn * x + c * y;
+                    const double zx = Z[i * 16 + p], zy = Z[i * 16 + q];
+                    Z[i * 16 + p] = c * zx - sn * zy;
+                    Z[i * 16 + q] = sn * zx + c * zy;
+                }
+            }
+            wave_order();
+        }
+    }
+}
+
+// One block round of the multi-workgroup one-sided Jacobi, by one workgroup: the 16 columns of
+// blocks P0 and Q0 (8 columns each, Q0 < 0 for none; columns at or past N are zero) of G and V
+// (column-major, ld N, global).  Their Gram matrix C = G_b^T G_b on the matrix cores (FP64 MFMA,
+// rows split over the wavefronts, partial tiles summed in wavefront order), its eigenvectors Z by
+// small_jacobi16 on one wavefront, then G_b <- G_b Z and V_b <- V_b Z on the matrix cores (a
+// wavefront per 16-row tile, in place): the same sweep over the 16 columns as rotating them pair
+// by pair, in 15 short rounds on 16 x 16 numbers and one product instead of 15 dependent rounds
+// over all N rows.  The update is skipped when no pair is
+// coupled above the rotation thresholds.  Returns 1 (to every thread) if a pair had relative
+// coupling above sqrt(tol), the sweep vote.
+template <int NT>
+__device__ __forceinline__ int gram_block_round(double *__restrict__ G, double *__restrict__ V, int N, int P0, int Q0,
+                                                double tol, double atol, char *dyn_lds) {
+    typedef Mma<double>::acc AC;
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    double *part = reinterpret_cast<double *>(dyn_lds);   // [NW][256]
+    double *C = part + NW * 256, *Z = C + 256, *rc = Z + 256, *rs = rc + 8;
+    int *rpq = reinterpret_cast<int *>(rs + 8), *flag = rpq + 8;
+    // local column c (0..15) -> global column, -1 if absent
+    auto gcol = [&](int c) -> int {
+        const int g = c < 8 ? P0 * 8 + c : (Q0 >= 0 ? Q0 * 8 + c - 8 : N);
+        return g < N ? g : -1;
+    };
+    const int myc = gcol(li);
+    // C = G_b^T G_b: chunk of 16 rows per 4 MFMA steps, lane group lg taking rows k0 + 4 lg + t;
+    // four chunks' loads in flight before their steps (the columns were last written by other
+    // workgroups, so each load waits on the memory side)
+    AC acc = (AC)0.0;
+    for (int base = wid * 16; base < N; base += NW * 64) {
+        double a[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = base + u * NW * 16 + 4 * lg + t;
+                a[u][t] = (myc >= 0 && k < N) ? G[(long long)myc * N + k] : 0.0;
+            }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc = Mma<double>::step(a[u][t], a[u][t], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[wid * 256 + Mma<double>::row(lg, r) * 16 + li] = acc[r];
+    __syncthreads();
+    if (tid < 256) {
+        double c = 0.0;
+        for (int w = 0; w < NW; ++w) c += part[w * 256 + tid];
+        C[tid] = c;
+    }
+    __syncthreads();
+    const double tol2 = tol * tol, atol2 = atol * atol;
+    if (wid == 0) {
+        // the pairs' couplings before the round: the sweep vote and whether to rotate at all
+        int big = 0, need = 0;
+        for (int e = lane; e < 256; e += 64) {
+            const int p = e >> 4, q = e & 15;
+            if (p < q) {
+                const double app = C[p * 16 + p], aqq = C[q * 16 + q], apq = C[e];
+                const double g2 = apq * apq;
+                if (g2 > atol2 * (app > aqq ? app : aqq)) {
+                    if (g2 > tol2 * (app * aqq)) need = 1;
+                    if (g2 > tol * (app * aqq)) big = 1;
+                }
+            }
+        }
+        need = __any(need);
+        big = __any(big);
+        if (need) small_jacobi16(C, Z, rc, rs, rpq, tol2, atol2);
+        if (lane == 0) {
+            flag[0] = need;
+            flag[1] = big;
+        }
+    }
+    __syncthreads();
+    const int need = flag[0], big = flag[1];
+    if (need) {
+        // G_b <- G_b Z and V_b <- V_b Z, one 16-row tile per wavefront at a time: lane group lg takes
+        // Z's rows 4 lg + t in step t; output row lg + 4 r, column li
+        const int nt = (N + 15) >> 4;
+        double b[4];
+        int cols[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            b[t] = Z[(4 * lg + t) * 16 + li];
+            cols[t] = gcol(4 * lg + t);
+        }
+        // eight tiles' loads in flight, then their steps and stores
+        for (int base = wid; base < 2 * nt; base += 8 * NW) {
+            double a[8][4];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int tile = base + u * NW;
+                const double *M = tile < nt ? G : V;
+                const int row = (tile < nt ? tile : tile - nt) * 16 + li;
+                const bool ok = tile < 2 * nt && row < N;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) a[u][t] = (ok && cols[t] >= 0) ? M[(long long)cols[t] * N + row] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int tile = base + u * NW;
+                if (tile >= 2 * nt) break;
+                double *M = tile < nt ? G : V;
+                const int r0 = (tile < nt ? tile : tile - nt) * 16;
+                AC d = (AC)0.0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) d = Mma<double>::step(a[u][t], b[t], d);
+                if (myc >= 0) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = r0 + Mma<double>::row(lg, r);
+                        if (i < N) M[(long long)myc * N + i] = d[r];
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    return big;
+}
+
 // P_{S+} of one block over the whole grid: G, V, W (N x N, column-major, ld N) and sigma (N) in
-// global scratch.  Block one-sided Jacobi: the columns form blocks of bcols; in each block round
-// (round-robin over the blocks, as the scalar form pairs columns) a workgroup takes a pair of
-// blocks into LDS and applies one cyclic sweep over all pairs of their 2 bcols columns, one
-// wavefront per column pair; a grid barrier ends the round.  Every pair of columns meets once per
-// sweep of block rounds; sweeps stop as in the single-workgroup forms (a sweep whose rotations all
-// had relative coupling at most sqrt(tol)), the vote collected in global memory.  Every workgroup
-// passes the same barriers: the same block rounds per sweep, and the same vote after the last.
+// global scratch.  Block one-sided Jacobi: the columns form blocks of 8; in each block round
+// (round-robin over the blocks, as the scalar form pairs columns) a workgroup orthogonalises the
+// 16 columns of a pair of blocks at once (gram_block_round); a grid barrier ends the round.  Every
+// pair of columns meets once per sweep of block rounds; sweeps stop as in the single-workgroup
+// forms (a sweep whose pairs all had relative coupling at most sqrt(tol)), the vote collected in
+// global memory.  Every workgroup passes the same barriers: the same block rounds per sweep, and
+// the same vote after the last.
 template <typename T, int NT>
 __device__ __noinline__ void coop_project_block(T *__restrict__ vs, T *__restrict__ us, int N, T *__restrict__ Vs,
                                                 bool warm, T *__restrict__ G, T *__restrict__ V, T *__restrict__ W,
-                                                T *__restrict__ sig, double *parts, CoopCtl *ctl, int bcols,
+                                                T *__restrict__ sig, double *parts, CoopCtl *ctl,
                                                 int max_sweeps, double jtol, char *dyn_lds, double *s_red,
                                                 double *s_red1, int *nsweeps, int &gsw) {
     typedef typename Lds<T>::type LT;
@@ -1780,9 +1968,7 @@ __device__ __noinline__ void coop_project_block(T *__restrict__ vs, T *__restric
     }
     const T tol = jacobi_tol<T>(jtol);
     const T atol = (T)(jacobi_atol_factor(N) * TS<T>::eps * sqrt(fro2));
-    const int nb = (N + bcols - 1) / bcols, nbp = nb + (nb & 1);
-    LT *lg = as_lds<T>(dyn_lds);                      // [2 bcols][N]
-    LT *lv = lg + (long long)2 * bcols * N;           // [2 bcols][N]
+    const int nb = (N + 7) / 8, nbp = nb + (nb & 1);
     __shared__ int s_big;
     int sweep = 0;
     while (sweep < max_sweeps) {
@@ -1796,38 +1982,9 @@ __device__ __noinline__ void coop_project_block(T *__restrict__ vs, T *__restric
             for (int pk = wg; pk < nbp / 2; pk += nwg) {
                 int P0, Q0;
                 rr_pair(R, pk, nbp, P0, Q0);
-                const int p0 = P0 * bcols, p1 = min(N, p0 + bcols);
-                const int q0 = Q0 < nb ? Q0 * bcols : 0, q1 = Q0 < nb ? min(N, q0 + bcols) : 0;
-                const int np = p1 - p0, c = np + (q1 - q0);
-                // local column lc: global column p0 + lc (lc < np) or q0 + lc - np
-                for (int idx = tid; idx < c * N; idx += NT) {
-                    const int lc = idx / N, i = idx - lc * N;
-                    const int col = lc < np ? p0 + lc : q0 + lc - np;
-                    lg[idx] = G[(long long)col * N + i];
-                    lv[idx] = V[(long long)col * N + i];
-                }
-                __syncthreads();
-                const int M2 = c + (c & 1);
-                int big = 0;
-                for (int r = 0; r < M2 - 1; ++r) {
-                    for (int kk = wid; kk < M2 / 2; kk += NW) {
-                        int p, q;
-                        rr_pair(r, kk, M2, p, q);
-                        if (q < c && wave_rotate_pair<T>(lg + (long long)p * N, lg + (long long)q * N, lv + (long long)p * N,
-                                                         lv + (long long)q * N, N, tol, atol) == 2)
-                            big = 1;
-                    }
-                    __syncthreads();
-                }
-                if (big && lane == 0) s_big = 1;
-                for (int idx = tid; idx < c * N; idx += NT) {
-                    const int lc = idx / N, i = idx - lc * N;
-                    const int col = lc < np ? p0 + lc : q0 + lc - np;
-                    G[(long long)col * N + i] = lg[idx];
-                    V[(long long)col * N + i] = lv[idx];
-                }
-                __syncthreads();
+                if (gram_block_round<NT>(G, V, N, P0, Q0 < nb ? Q0 : -1, tol, atol, dyn_lds) && tid == 0) s_big = 1;
             }
+            __syncthreads();
             if (R == nbp - 2 && tid == 0 && s_big)
                 __hip_atomic_store(&ctl->big[fl], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             grid_sync(ctl);
@@ -2045,7 +2202,7 @@ __device__ __noinline__ void coop_affine_phase(const ProbDesc &P, const RunParam
 
 // Whole FP64 iterations of one problem over a cooperative grid (see sos_launch_admm_coop).
 template <int NT>
-__global__ __launch_bounds__(NT) void admm_coop(RunParams rp, CoopCtl *ctl, double *scr, int bcols) {
+__global__ __launch_bounds__(NT) void admm_coop(RunParams rp, CoopCtl *ctl, double *scr) {
     typedef double T;
     __shared__ double s_red[4 * (NT / 64)];
     __shared__ double s_red1;
@@ -2075,7 +2232,7 @@ __global__ __launch_bounds__(NT) void admm_coop(RunParams rp, CoopCtl *ctl, doub
         for (int bk = 0; bk < P.nblk; ++bk) {
             const int off = P.blk_off[bk], N = P.blk_N[bk];
             coop_project_block<T, NT>(v + off, u + off, N, rp.warm_eig ? vstore + voff : nullptr, rp.warm_eig && warm, G, V,
-                                      W, sig, parts, ctl, bcols, rp.max_sweeps, rp.jacobi_tol, dyn_lds, s_red, &s_red1,
+                                      W, sig, parts, ctl, rp.max_sweeps, rp.jacobi_tol, dyn_lds, s_red, &s_red1,
                                       &s_sweeps, gsw);
             voff += (long long)N * N;
         }
@@ -2515,16 +2672,14 @@ int sos_static_scratch(void **ptr) {
     return 0;
 }
 
-// dynamic LDS of a cooperative launch: the affine step's k-vector and partial sums, or the
-// Jacobi blocks' columns of G and V (the two phases are separated by barriers)
-// dynamic LDS of admm_coop: two column blocks of G and V (the affine step keeps its k-vectors in
-// global scratch)
-static size_t coop_lds_bytes(const RunParams &rp, int bcols) {
-    return sizeof(double) * 4 * (size_t)bcols * rp.eig_ld;
+// dynamic LDS of admm_coop: the block round's Gram tiles and rotations (the affine step keeps its
+// k-vectors in global scratch)
+static size_t coop_lds_bytes(int threads) {
+    return gram_round_lds_bytes(threads);
 }
 
-int sos_coop_max_grid(int threads, const RunParams &rp, int bcols) {
-    const size_t lds = coop_lds_bytes(rp, bcols);
+int sos_coop_max_grid(int threads, const RunParams &rp) {
+    const size_t lds = coop_lds_bytes(threads);
     if (lds > (size_t)rp.lds_budget) return 0;
     int dev = 0, coop = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -2548,15 +2703,14 @@ int sos_coop_max_grid(int threads, const RunParams &rp, int bcols) {
     return g < SOS_COOP_MAX_WG ? g : SOS_COOP_MAX_WG;
 }
 
-int sos_launch_admm_coop(int threads, int grid, const RunParams &rp_in, CoopCtl *ctl, double *scratch, int bcols,
-                         void *stream) {
+int sos_launch_admm_coop(int threads, int grid, const RunParams &rp_in, CoopCtl *ctl, double *scratch, void *stream) {
     RunParams rp = rp_in;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (grid < 1 || grid > SOS_COOP_MAX_WG || bcols < 1) return -1;
-    const size_t lds = coop_lds_bytes(rp, bcols);
+    if (grid < 1 || grid > SOS_COOP_MAX_WG) return -1;
+    const size_t lds = coop_lds_bytes(threads);
     if (!launch_precheck()) return -4;
     hipLaunchKernelGGL(reset_coop, dim3(1), dim3(64), 0, st, ctl);
-    void *args[] = {&rp, &ctl, &scratch, &bcols};
+    void *args[] = {&rp, &ctl, &scratch};
     hipError_t e;
     switch (threads) {
         case 256:
