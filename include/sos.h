@@ -212,6 +212,16 @@ int sos_set_iterate(sos_work *w, const double *u, const double *v);
    SOS_E_INVAL for a bad block index or dual; SOS_E_STATE if tau == 0. */
 int sos_psd_factor(sos_work *w, int32_t block, int32_t dual, double *evals, double *evecs);
 
+/* The eigenvectors the projection keeps for its warm start (Section IV-A's projection step:
+   each iteration's Jacobi starts from the last iteration's eigenvectors of the block): block
+   `block`'s N x N matrix (column-major, columns = eigenvectors) from the cache of the given
+   precision (SOS_FP64: the FP64 iterations', SOS_FP32_MIXED: the FP32 bulk iterations'), copied
+   into V (N^2 doubles, host memory, caller-owned).  *valid (may be NULL) is 1 if the cache holds
+   the eigenvectors of the last iteration, 0 after a reset or before the first iteration (the
+   contents are then stale).  For diagnostics, e.g. the orthogonality of the cached basis.
+   SOS_E_INVAL for a bad block index or precision. */
+int sos_get_eig_cache(const sos_work *w, int32_t block, int32_t precision, double *V, int32_t *valid);
+
 /* Message for the last error on w (or on the last failed sos_setup when w is NULL). */
 const char *sos_last_error(const sos_work *w);
 

@@ -23,7 +23,8 @@ SOS_PART_PAPER, SOS_PART_COLUMNS = 0, 1
 STATUS_NAMES = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_infeasible", 4: "max_iters"}
 
 EXPORTED = ["sos_default_settings", "sos_setup", "sos_step", "sos_step_static", "sos_solve", "sos_warm_start",
-            "sos_get_solution", "sos_get_iterate", "sos_set_iterate", "sos_psd_factor", "sos_last_error", "sos_free",
+            "sos_get_solution", "sos_get_iterate", "sos_set_iterate", "sos_psd_factor", "sos_get_eig_cache",
+            "sos_last_error", "sos_free",
             "sos_batch_setup", "sos_batch_solve", "sos_batch_reset", "sos_batch_last_ms", "sos_batch_last_error",
             "sos_batch_phase_ms", "sos_batch_free", "sos_layout_size", "sos_batch_warm_start",
             "sos_batch_export_solutions", "sos_mlp_create", "sos_mlp_num_params", "sos_mlp_set_params",
@@ -96,6 +97,7 @@ def load():
     lib.sos_get_iterate.argtypes = [vp, P(C.c_double), P(C.c_double)]
     lib.sos_set_iterate.argtypes = [vp, P(C.c_double), P(C.c_double)]
     lib.sos_psd_factor.argtypes = [vp, C.c_int32, C.c_int32, P(C.c_double), P(C.c_double)]
+    lib.sos_get_eig_cache.argtypes = [vp, C.c_int32, C.c_int32, P(C.c_double), P(C.c_int32)]
     lib.sos_last_error.argtypes = [vp]
     lib.sos_last_error.restype = C.c_char_p
     lib.sos_free.argtypes = [vp]
@@ -272,6 +274,16 @@ def sos_psd_factor(w: Work, block: int, dual: bool = False):
     vec = np.empty(N * N)
     _check(load().sos_psd_factor(w.handle, int(block), int(bool(dual)), _dptr(lam), _dptr(vec)), w.handle)
     return lam, vec.reshape(N, N, order="F")
+
+
+def sos_get_eig_cache(w: Work, block: int, precision: int = SOS_FP64):
+    """(V (N x N, columns = the cached eigenvectors of block `block`), valid) from the warm-start
+    cache of the given precision."""
+    N = int(w.psd_dims[block]) if 0 <= block < len(w.psd_dims) else 1
+    vec = np.empty(N * N)
+    valid = C.c_int32(0)
+    _check(load().sos_get_eig_cache(w.handle, int(block), int(precision), _dptr(vec), C.byref(valid)), w.handle)
+    return vec.reshape(N, N, order="F"), bool(valid.value)
 
 
 def sos_free(w: Work) -> None:

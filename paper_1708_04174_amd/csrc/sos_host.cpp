@@ -1105,6 +1105,31 @@ int sos_psd_factor(sos_work *w, int32_t block, int32_t dual, double *evals, doub
     });
 }
 
+int sos_get_eig_cache(const sos_work *w, int32_t block, int32_t precision, double *V, int32_t *valid) {
+    if (!w || !V) return SOS_E_INVAL;
+    return guarded(const_cast<sos_work *>(w), [&] {
+        if (block < 0 || block >= (int)w->N.size()) throw Status(SOS_E_INVAL, "block index out of range");
+        if (precision != SOS_FP64 && precision != SOS_FP32_MIXED)
+            throw Status(SOS_E_INVAL, "precision must be SOS_FP64 or SOS_FP32_MIXED");
+        long long off = 0;
+        for (int b = 0; b < block; ++b) off += (long long)w->N[b] * w->N[b];
+        const size_t nn = (size_t)w->N[block] * w->N[block];
+        if (precision == SOS_FP64) {
+            hip_check(hipMemcpyAsync(V, w->desc.vs64 + off, sizeof(double) * nn, hipMemcpyDeviceToHost, w->stream), "copy");
+        } else {
+            std::vector<float> f(nn);
+            hip_check(hipMemcpyAsync(f.data(), w->desc.vs32 + off, sizeof(float) * nn, hipMemcpyDeviceToHost, w->stream),
+                      "copy");
+            hip_check(hipStreamSynchronize(w->stream), "sync");
+            for (size_t i = 0; i < nn; ++i) V[i] = f[i];
+        }
+        double tk3[3];
+        hip_check(hipMemcpyAsync(tk3, w->desc.tk, sizeof(tk3), hipMemcpyDeviceToHost, w->stream), "copy");
+        hip_check(hipStreamSynchronize(w->stream), "sync");
+        if (valid) *valid = tk3[2] != 0.0 ? 1 : 0;
+    });
+}
+
 const char *sos_last_error(const sos_work *w) { return w ? w->err.c_str() : g_setup_error.c_str(); }
 
 void sos_free(sos_work *w) {
