@@ -1663,28 +1663,29 @@ __global__ __launch_bounds__(NT, 2) void admm_mixed(RunParams rp32, RunParams rp
 // co-resident under a cooperative launch), with a bounded wait so that a missing workgroup
 // ends the launch with an error flag instead of a hang.
 __device__ __forceinline__ void grid_sync(CoopCtl *ctl) {
-    __syncthreads();
+    __syncthreads();   // the workgroup's writes are ordered before thread 0's arrival
     if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned int g = __hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned int g = __hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // arrival: an agent-scope release (publishes the workgroup's writes) and acquire
         const unsigned int arrived = __hip_atomic_fetch_add(&ctl->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (arrived == gridDim.x - 1) {
             __hip_atomic_store(&ctl->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&ctl->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             // bounded wait (about a second, far beyond any barrier of a working launch); once a wait
-            // has timed out, later barriers do not wait at all, so a broken launch still ends soon
+            // has timed out, later barriers do not wait at all, so a broken launch still ends soon.
+            // Polls are relaxed; one acquire fence after the release of the generation is seen
             long long spins = 0;
-            while (__hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g &&
+            while (__hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g &&
                    !__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > (1LL << 24)) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (1LL << 25)) {
                     __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        __threadfence();
     }
     __syncthreads();
 }
@@ -1734,67 +1735,61 @@ __device__ __forceinline__ int wave_rotate_pair(typename Lds<T>::type *gp, typen
     return ga * ga > tol * (al * be) ? 2 : 1;
 }
 
-// Dynamic LDS of gram_block_round for NT threads: NT / 64 partial Gram tiles, the Gram matrix C,
-// its eigenvectors Z (16 x 16 each), the rotations of one round and two flags.
+// Dynamic LDS of gram_block_round for NT threads: NT / 64 partial Gram tiles, the Gram matrix C
+// and the accumulated rotation Z (16 x 16 each), two flags.
 __host__ __device__ constexpr size_t gram_round_lds_bytes(int nt) {
-    return sizeof(double) * ((size_t)(nt / 64) * 256 + 2 * 256 + 2 * 8) + sizeof(int) * (8 + 2);
+    return sizeof(double) * ((size_t)(nt / 64) * 256 + 2 * 256) + sizeof(int) * 2;
 }
 
 // One cyclic sweep of two-sided Jacobi on the 16 x 16 symmetric C (row-major, LDS) by one
 // wavefront, accumulating the rotations in Z (set to I here): round-robin order, 8 disjoint
-// rotations per round (rows, then columns of C, then columns of Z).  Since C = G_b^T G_b, rotating C
+// rotations per round (rows, then columns of C, then columns of Z); lane l applies the rotations
+// of pairs l / 16 and 4 + l / 16 to row or column l % 16 and computes their angles itself.  Since C = G_b^T G_b, rotating C
 // on both sides by the rotation of columns p, q is that column rotation seen through the Gram
 // matrix: the sweep is the one-sided sweep over the 16 columns, done on 16 x 16 numbers instead of
 // on N-long columns.  A pair is rotated by jacobi_rot (same thresholds and angle as a column pair
 // of the one-sided form).
-__device__ __forceinline__ void small_jacobi16(double *C, double *Z, double *rc, double *rs, int *rpq, double tol2,
-                                               double atol2) {
+__device__ __forceinline__ void small_jacobi16(double *C, double *Z, double tol2, double atol2) {
     const int lane = threadIdx.x & 63;
     for (int e = lane; e < 256; e += 64) Z[e] = (e >> 4) == (e & 15) ? 1.0 : 0.0;
     wave_order();
-    {
-        for (int r = 0; r < 15; ++r) {
-            if (lane < 8) {
-                int p, q;
-                rr_pair(r, lane, 16, p, q);
-                double c = 1.0, sn = 0.0;
-                if (!jacobi_rot<double>(C[p * 16 + p], C[q * 16 + q], C[p * 16 + q], tol2, atol2, c, sn)) {
-                    c = 1.0;
-                    sn = 0.0;
-                }
-                rc[lane] = c;
-                rs[lane] = sn;
-                rpq[lane] = p | (q << 8);
+    const int j = lane & 15;   // this lane's column (row phase) and row (column phase)
+    for (int r = 0; r < 15; ++r) {
+        // the two pairs this lane works on, k = lane / 16 and 4 + lane / 16, each rotation computed
+        // by the 16 lanes that apply it (no exchange of angles)
+        int p[2], q[2];
+        double c[2], sn[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            rr_pair(r, (lane >> 4) + 4 * h, 16, p[h], q[h]);
+            if (!jacobi_rot<double>(C[p[h] * 16 + p[h]], C[q[h] * 16 + q[h]], C[p[h] * 16 + q[h]], tol2, atol2, c[h],
+                                    sn[h])) {
+                c[h] = 1.0;
+                sn[h] = 0.0;
             }
-            wave_order();
-            if (!__any(lane < 8 && rs[lane & 7] != 0.0)) continue;
-            for (int task = lane; task < 128; task += 64) {   // rows p, q of C: J^T C
-                const int k = task >> 4, j = task & 15;
-                const double sn = rs[k];
-                if (sn != 0.0) {
-                    const int p = rpq[k] & 255, q = rpq[k] >> 8;
-                    const double c = rc[k], x = C[p * 16 + j], y = C[q * 16 + j];
-                    C[p * 16 + j] = c * x - sn * y;
-                    C[q * 16 + j] = sn * x + c * y;
-                }
-            }
-            wave_order();
-            for (int task = lane; task < 128; task += 64) {   // columns p, q of C and Z: C J, Z J
-                const int k = task >> 4, i = task & 15;
-                const double sn = rs[k];
-                if (sn != 0.0) {
-                    const int p = rpq[k] & 255, q = rpq[k] >> 8;
-                    const double c = rc[k];
-                    const double x = C[i * 16 + p], y = C[i * 16 + q];
-                    C[i * 16 + p] = c * x - sn * y;
-                    C[i * 16 + q] = sn * x + c * y;
-                    const double zx = Z[i * 16 + p], zy = Z[i * 16 + q];
-                    Z[i * 16 + p] = c * zx - sn * zy;
-                    Z[i * 16 + q] = sn * zx + c * zy;
-                }
-            }
-            wave_order();
         }
+        wave_order();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {   // rows p, q of C: J^T C
+            if (sn[h] != 0.0) {
+                const double x = C[p[h] * 16 + j], y = C[q[h] * 16 + j];
+                C[p[h] * 16 + j] = c[h] * x - sn[h] * y;
+                C[q[h] * 16 + j] = sn[h] * x + c[h] * y;
+            }
+        }
+        wave_order();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {   // columns p, q of C and Z: C J, Z J
+            if (sn[h] != 0.0) {
+                const double x = C[j * 16 + p[h]], y = C[j * 16 + q[h]];
+                C[j * 16 + p[h]] = c[h] * x - sn[h] * y;
+                C[j * 16 + q[h]] = sn[h] * x + c[h] * y;
+                const double zx = Z[j * 16 + p[h]], zy = Z[j * 16 + q[h]];
+                Z[j * 16 + p[h]] = c[h] * zx - sn[h] * zy;
+                Z[j * 16 + q[h]] = sn[h] * zx + c[h] * zy;
+            }
+        }
+        wave_order();
     }
 }
 
@@ -1816,8 +1811,8 @@ __device__ __forceinline__ int gram_block_round(double *__restrict__ G, double *
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
     double *part = reinterpret_cast<double *>(dyn_lds);   // [NW][256]
-    double *C = part + NW * 256, *Z = C + 256, *rc = Z + 256, *rs = rc + 8;
-    int *rpq = reinterpret_cast<int *>(rs + 8), *flag = rpq + 8;
+    double *C = part + NW * 256, *Z = C + 256;
+    int *flag = reinterpret_cast<int *>(Z + 256);
     // local column c (0..15) -> global column, -1 if absent
     auto gcol = [&](int c) -> int {
         const int g = c < 8 ? P0 * 8 + c : (Q0 >= 0 ? Q0 * 8 + c - 8 : N);
@@ -1868,7 +1863,6 @@ __device__ __forceinline__ int gram_block_round(double *__restrict__ G, double *
         }
         need = __any(need);
         big = __any(big);
-        if (need) small_jacobi16(C, Z, rc, rs, rpq, tol2, atol2);
         if (lane == 0) {
             flag[0] = need;
             flag[1] = big;
@@ -1877,21 +1871,18 @@ __device__ __forceinline__ int gram_block_round(double *__restrict__ G, double *
     __syncthreads();
     const int need = flag[0], big = flag[1];
     if (need) {
-        // G_b <- G_b Z and V_b <- V_b Z, one 16-row tile per wavefront at a time: lane group lg takes
-        // Z's rows 4 lg + t in step t; output row lg + 4 r, column li
+        // G_b <- G_b Z and V_b <- V_b Z: a 16-row tile per wavefront at a time, lane group lg taking
+        // Z's rows 4 lg + t in step t; output row lg + 4 r, column li.  Wavefront 0 computes Z (one
+        // inner sweep) while the others load their first four tiles; then four tiles' loads in
+        // flight at a time
         const int nt = (N + 15) >> 4;
-        double b[4];
         int cols[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            b[t] = Z[(4 * lg + t) * 16 + li];
-            cols[t] = gcol(4 * lg + t);
-        }
-        // eight tiles' loads in flight, then their steps and stores
-        for (int base = wid; base < 2 * nt; base += 8 * NW) {
-            double a[8][4];
+        for (int t = 0; t < 4; ++t) cols[t] = gcol(4 * lg + t);
+        double a[4][4];
+        auto load_batch = [&](int base) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 4; ++u) {
                 const int tile = base + u * NW;
                 const double *M = tile < nt ? G : V;
                 const int row = (tile < nt ? tile : tile - nt) * 16 + li;
@@ -1899,8 +1890,17 @@ __device__ __forceinline__ int gram_block_round(double *__restrict__ G, double *
 #pragma unroll
                 for (int t = 0; t < 4; ++t) a[u][t] = (ok && cols[t] >= 0) ? M[(long long)cols[t] * N + row] : 0.0;
             }
+        };
+        if (wid == 0) small_jacobi16(C, Z, tol2, atol2);
+        else load_batch(wid);
+        __syncthreads();
+        double b[4];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+        for (int t = 0; t < 4; ++t) b[t] = Z[(4 * lg + t) * 16 + li];
+        for (int base = wid; base < 2 * nt; base += 4 * NW) {
+            if (wid == 0 || base != wid) load_batch(base);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
                 const int tile = base + u * NW;
                 if (tile >= 2 * nt) break;
                 double *M = tile < nt ? G : V;
