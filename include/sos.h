@@ -100,11 +100,13 @@ typedef struct {
                                 form for every block, 3 = the multi-workgroup form for every block.
                                 In SOS_FP64, eig_form 0 also runs a single problem whose largest
                                 block has N >= 128 as one cooperative launch over several workgroups:
-                                workgroup 0 takes the affine step and the residual checks, all of
-                                them a block one-sided Jacobi (column blocks of up to 8 columns, one
-                                workgroup per pair of blocks and block round, a grid barrier per
-                                round) and the MFMA products (a solve with warm_budget > 0 stays on
-                                one workgroup).  Batches take theirs from the schedule.
+                                all of them take the affine step (a grid barrier between its
+                                phases), a block one-sided Jacobi (column blocks of 8 columns, one
+                                workgroup per pair of blocks and block round, the pair's 16 x 16
+                                Gram matrix and rotation on the matrix cores, a grid barrier per
+                                round) and the MFMA products; workgroup 0 the residual checks (a
+                                solve with warm_budget > 0 stays on one workgroup).  Batches take
+                                theirs from the schedule.
                                 Out of 0..3: SOS_E_INVAL. */
     int32_t warm_budget;     /* 0: a warm-started solve keeps its start to the end.  > 0: a solve that
                                 starts from sos_warm_start / sos_batch_warm_start and has neither

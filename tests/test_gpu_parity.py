@@ -547,3 +547,24 @@ def test_cached_eigenvectors_stay_orthogonal(B):
     print(f"[parity] cached eigenvector orthogonality (FP32): {errs}", flush=True)
     # FP32 columns are orthonormal to about N eps_32 after one rebuild; drift stays within 1e-4
     assert max(errs.values()) <= 1e-4
+
+
+def test_multi_workgroup_runs_are_bitwise_equal(B):
+    # the grid-wide affine step and the Gram-based block rounds sum in fixed orders: two solves of
+    # the same problem on the cooperative form give the same bits
+    prob = F.example_pop(16)
+    outs = []
+    for _ in range(2):
+        w = B.setup_problem(prob, B.sos_default_settings(tol=1e-6, max_iters=3000, eig_form=3))
+        inf = B.sos_solve(w)
+        u, v = B.sos_get_iterate(w)
+        V, valid = B.sos_get_eig_cache(w, 0, B.SOS_FP64)
+        w.free()
+        outs.append((inf["iters"], u, v))
+    assert outs[0][0] == outs[1][0]
+    assert np.array_equal(outs[0][1], outs[1][1]) and np.array_equal(outs[0][2], outs[1][2])
+    # the cached FP64 eigenvectors of the cooperative form stay orthonormal to rounding (they are
+    # rotated by products with the blocks' 16 x 16 rotations and never re-orthonormalised)
+    orth = float(np.max(np.abs(V.T @ V - np.eye(V.shape[0]))))
+    print(f"[parity] multi-workgroup: {outs[0][0]} iterations twice, cached V orthogonality {orth:.2e}", flush=True)
+    assert valid and orth <= 1e-10
