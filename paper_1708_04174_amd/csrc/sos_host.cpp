@@ -139,6 +139,7 @@ struct sos_batch {
     void *d_work = nullptr, *d_eig = nullptr;
     long long work_stride = 0, eig_stride = 0;
     int eig_ld = 0, threads = 256, grid = 1, count = 0, fp64 = 1, wg_per_cu = 2, max_sweeps = 40;
+    int pair_need = 0;   // LDS elements of the largest two-block problem's blocks together
     int max_len = 0;
     hipStream_t stream = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -683,6 +684,7 @@ RunParams single_params(sos_work *w, int mode, int iters, int min_iters, double 
     rp.eig_wave = w->st.eig_form == 2 ? 0 : 2;
     rp.rows_nmin = w->st.eig_form == 0 ? kRowsNmin : 0;
     rp.jac_block = kJacBlock;
+    rp.pair_need = w->N.size() == 2 ? (int)sos_pair_need(w->N[0], w->N[1]) : 0;
     return rp;
 }
 
@@ -1221,6 +1223,10 @@ int sos_batch_setup(int32_t count, sos_work *const *probs, const char *schedule_
         const int cus = device_cu_count();
         B->grid = std::min(count, cus * B->wg_per_cu);
         B->eig_ld = nmax;
+        B->pair_need = 0;
+        for (int i = 0; i < count; ++i)
+            if (probs[i]->N.size() == 2)
+                B->pair_need = std::max(B->pair_need, (int)sos_pair_need(probs[i]->N[0], probs[i]->N[1]));
         B->work_stride = (long long)(((mmax + 63) & ~63) + nxmax + 64 + tailmax) * sizeof(double);
         B->eig_stride = (long long)3 * B->eig_ld * nmax * sizeof(double) + 256;
         B->d_work = B->mem.alloc<char>((size_t)B->work_stride * B->grid);
@@ -1259,6 +1265,7 @@ static RunParams batch_params(sos_batch *B, int mode, int iters, int min_iters, 
     rp.eig = B->d_eig;
     rp.eig_stride = B->eig_stride;
     rp.eig_ld = B->eig_ld;
+    rp.pair_need = B->pair_need;
     rp.max_sweeps = B->max_sweeps;
     rp.warm_eig = B->warm_eig;
     rp.eig_wave = B->eig_wave;

@@ -114,8 +114,25 @@ struct RunParams {
     double jacobi_tol;      // relative coupling a Jacobi pair must exceed to be rotated (0: 16 eps of the type)
     int jac_block;          // 8: the lane-group form sweeps in the block-cyclic order when G and V sit in
                             //    LDS (a workgroup barrier per block round); 0: the cyclic order
+    int pair_need;          // LDS elements (of the launch's type) that G and V of a two-block problem's
+                            //    blocks need together (the largest over the problems; 0: none)
+    int lds_pair;           // filled in by the launcher: pair_need if the launch's LDS holds it, else 0;
+                            //    a two-block problem that fits projects both blocks at once
     unsigned long long *ts; // optional [start, end] wall-clock stamps of the launch (min / max over workgroups)
 };
+
+// Leading dimension of an N x N eigensolver matrix in LDS: columns padded to 8 mod 16 elements,
+// so that a wavefront's reads of a round's columns fall in distinct banks.
+#define SOS_LDS_LD(N) ((N) <= 8 ? (N) : ((((N) + 7) & ~15) + 8))
+// LDS elements that G and V of two blocks N1, N2 take together (0 unless both are at least 2);
+// host and device code share it
+#if defined(__HIP__)
+__host__ __device__
+#endif
+static inline long long sos_pair_need(int N1, int N2) {
+    if (N1 < 2 || N2 < 2) return 0;
+    return 2LL * ((long long)N1 * SOS_LDS_LD(N1) + (long long)N2 * SOS_LDS_LD(N2));
+}
 
 // Control block of a cooperative (multi-workgroup) launch on one problem, in device memory.
 struct CoopCtl {

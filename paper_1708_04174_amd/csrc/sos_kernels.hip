@@ -385,7 +385,7 @@ __device__ __forceinline__ void rr_pair(int r, int kk, int M, int &p, int &q) {
 // each); with this stride the 8 column starts fall 8 banks apart modulo 64 banks (4-byte
 // elements), and 16 apart within each half-wavefront for 8-byte elements, so the groups'
 // reads of a column do not share banks.
-__host__ __device__ __forceinline__ int lds_ld(int N) { return N <= 8 ? N : ((N + 7) & ~15) + 8; }
+__host__ __device__ __forceinline__ int lds_ld(int N) { return SOS_LDS_LD(N); }
 
 __device__ __forceinline__ int lanes_per_pair(const RunParams &rp, int N) {
     const int b = N < 32 ? 0 : N < 64 ? 1 : N < 96 ? 2 : N < 128 ? 3 : N < 192 ? 4 : N < 256 ? 5 : 6;
@@ -865,27 +865,84 @@ __device__ __forceinline__ int block_cyclic_sweep(LP G, LP V, int ld, int N, T t
     return big;
 }
 
-template <typename T, int NT, typename GP, typename VP>
-__device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ us, int N, T *__restrict__ Vs, bool warm, GP G,
-                              VP V, int ld, T *__restrict__ Tm, typename Lds<T>::type *s_sig, const EigScratch &sc,
-                              int max_sweeps, int gs = 16, int jblock = 0) {
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+// One block-cyclic sweep (block_cyclic_sweep) of each of two matrices at once, G and V of both in
+// LDS: the blocks of both share the passes of the in-block phase (a wavefront per block) and the
+// block rounds share their workgroup barriers (the two matrices' block pairs spread over the
+// wavefronts), so the smaller matrix's sweep runs on wavefronts the larger one leaves idle.  Each
+// matrix's rotations and their order are those of its own sweep.  A matrix with act = 0 is left
+// alone.  big1, big2: as block_cyclic_sweep's result, per matrix.
+template <typename T, int NT, typename LP>
+__device__ __forceinline__ void block_cyclic_sweep2(LP G1, LP V1, int ld1, int N1, T tol1, T atol1, bool act1, LP G2,
+                                                    LP V2, int ld2, int N2, T tol2, T atol2, bool act2, int &big1,
+                                                    int &big2) {
     constexpr int NW = NT / 64;
-    if (N == 1) {
-        if (tid == 0) {
-            const T w = vs[0];
-            const T x = w > (T)0 ? w : (T)0;
-            us[0] = x;
-            vs[0] = x - w;
-            if (Vs) Vs[0] = (T)1;
+    const int wid = threadIdx.x >> 6, grp = (threadIdx.x & 63) >> 3;
+    const int nb1 = act1 ? (N1 + 7) >> 3 : 0, nb2 = act2 ? (N2 + 7) >> 3 : 0;
+    const int nbp1 = nb1 + (nb1 & 1), nbp2 = nb2 + (nb2 & 1);
+    big1 = big2 = 0;
+    for (int Bk = wid; Bk < nb1 + nb2; Bk += NW) {
+        const bool one = Bk < nb1;
+        LP G = one ? G1 : G2;
+        LP V = one ? V1 : V2;
+        const int ld = one ? ld1 : ld2, N = one ? N1 : N2;
+        const T tol = one ? tol1 : tol2, atol = one ? atol1 : atol2;
+        const int c0 = (one ? Bk : Bk - nb1) * 8, c = N - c0 < 8 ? N - c0 : 8, M = c + (c & 1);
+        for (int r = 0; r < M - 1; ++r) {
+            if (grp < M / 2) {
+                int p, q;
+                rr_pair(r, grp, M, p, q);
+                if (q < c && os_rotate_pair<T, 8, LP, LP>(G, ld, V, ld, N, c0 + p, c0 + q, tol, atol) == 2) {
+                    if (one) big1 = 1;
+                    else big2 = 1;
+                }
+            }
+            wave_order();
+        }
+    }
+    __syncthreads();
+    const int rounds = (nbp1 > nbp2 ? nbp1 : nbp2) - 1;
+    const int h1 = nbp1 / 2, h2 = nbp2 / 2;
+    for (int R = 0; R < rounds; ++R) {
+        const int n1 = R < nbp1 - 1 ? h1 : 0, n2 = R < nbp2 - 1 ? h2 : 0;
+        for (int pk = wid; pk < n1 + n2; pk += NW) {
+            const bool one = pk < n1;
+            const int nb = one ? nb1 : nb2, nbp = one ? nbp1 : nbp2, N = one ? N1 : N2;
+            int P, Q;
+            rr_pair(R, one ? pk : pk - n1, nbp, P, Q);
+            if (Q >= nb) continue;
+            LP G = one ? G1 : G2;
+            LP V = one ? V1 : V2;
+            const int ld = one ? ld1 : ld2;
+            const T tol = one ? tol1 : tol2, atol = one ? atol1 : atol2;
+            int b = 0;
+            if (N <= 32) b = cross_block_regs<T, 4, true>(G, V, ld, N, P, Q, tol, atol);
+            else if (N <= 64) b = cross_block_regs<T, 8, false>(G, V, ld, N, P, Q, tol, atol);
+            else if (N <= 96) b = cross_block_regs<T, 12, false>(G, V, ld, N, P, Q, tol, atol);
+            else
+                for (int st = 0; st < 8; ++st) {
+                    const int p = P * 8 + grp, q = Q * 8 + ((grp + st) & 7);
+                    if (p < N && q < N && os_rotate_pair<T, 8, LP, LP>(G, ld, V, ld, N, p, q, tol, atol) == 2) b = 1;
+                    wave_order();
+                }
+            if (b) {
+                if (one) big1 = 1;
+                else big2 = 1;
+            }
         }
         __syncthreads();
-        return;
     }
-    // G = W (cold, V = I) or G = W V_prev (warm); W is symmetric, so column j of W = row j.
-    // Warm, with at most kMfmaHold 16 x 16 tiles of G per wavefront, W is staged where G goes
-    // and each wavefront keeps its tiles of W V in registers until every read of W is done;
-    // otherwise W is staged in the global scratch Tm.
+}
+
+// Stages one block for the Jacobi sweeps: G = W (cold, V = I) or G = W V_prev (warm), W symmetric
+// (column j of W = row j), read from the packed lower triangle vs.  Warm, with at most kMfmaHold
+// 16 x 16 tiles of G per wavefront, W is staged where G goes and each wavefront keeps its tiles of
+// W V in registers until every read of W is done; otherwise W is staged in the global scratch Tm.
+// Returns |W|_F^2 (every thread).
+template <typename T, int NT, typename GP, typename VP>
+__device__ __forceinline__ double stage_block(T *__restrict__ vs, int N, T *__restrict__ Vs, bool warm, GP G, VP V,
+                                              int ld, T *__restrict__ Tm, const EigScratch &sc) {
+    const int tid = threadIdx.x;
+    constexpr int NW = NT / 64;
     const int nt16 = (N + 15) >> 4;
     const bool wreg = warm && nt16 * nt16 <= NW * kMfmaHold;
     // four entries per thread and pass, their global reads issued together
@@ -926,14 +983,102 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
         __syncthreads();
     }
     block_sum2<NT>(fro2, dummy, sc.s_red);
+    return fro2;
+}
+
+// One Jacobi sweep of one block (see project_block); returns 1 (in the threads that saw one) if a
+// rotation had relative coupling above sqrt(tol).
+template <typename T, int NT, typename GP, typename VP>
+__device__ __forceinline__ int sweep_block(GP G, VP V, int ld, int N, T tol, T atol, int gs, int jblock) {
+    const int tid = threadIdx.x;
+    const int M = N + (N & 1);
+    const int H = M / 2;
+    int big = 0;
+    constexpr bool kBothLds = std::is_same<GP, typename Lds<T>::type *>::value && std::is_same<VP, GP>::value;
+    // lanes per column pair: a tile choice per block-size bucket (autotuned), or the
+    // block-cyclic order (G and V in LDS)
+    if (kBothLds && jblock == 8) {
+        if constexpr (kBothLds) big = block_cyclic_sweep<T, NT>(G, V, ld, N, tol, atol);
+    } else if (gs == 8) {
+        const int grp = tid / 8;
+        for (int r = 0; r < M - 1; ++r) {
+            for (int kk = grp; kk < H; kk += NT / 8) {
+                int p, q;
+                rr_pair(r, kk, M, p, q);
+                if (q < N && os_rotate_pair<T, 8, GP, VP>(G, ld, V, ld, N, p, q, tol, atol) == 2) big = 1;
+            }
+            __syncthreads();
+        }
+    } else if (gs == 32) {
+        const int grp = tid / 32;
+        for (int r = 0; r < M - 1; ++r) {
+            for (int kk = grp; kk < H; kk += NT / 32) {
+                int p, q;
+                rr_pair(r, kk, M, p, q);
+                if (q < N && os_rotate_pair<T, 32, GP, VP>(G, ld, V, ld, N, p, q, tol, atol) == 2) big = 1;
+            }
+            __syncthreads();
+        }
+    } else {
+        const int grp = tid / 16;
+        for (int r = 0; r < M - 1; ++r) {
+            for (int kk = grp; kk < H; kk += NT / 16) {
+                int p, q;
+                rr_pair(r, kk, M, p, q);
+                if (q < N && os_rotate_pair<T, 16, GP, VP>(G, ld, V, ld, N, p, q, tol, atol) == 2) big = 1;
+            }
+            __syncthreads();
+        }
+    }
+    return big;
+}
+
+// sigma_j = |g_j|, then u = lower((W + V Sigma V^T) / 2), v = u - w on the matrix cores, and the
+// eigenvectors into the warm-start cache Vs.
+template <typename T, int NT, typename GP, typename VP>
+__device__ __forceinline__ void finish_block(T *__restrict__ vs, T *__restrict__ us, int N, T *__restrict__ Vs, GP G,
+                                             VP V, int ld, typename Lds<T>::type *s_sig) {
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr int NW = NT / 64;
+    for (int j = wid; j < N; j += NW) {
+        T s = 0;
+        for (int i = lane; i < N; i += 64) s += G[j * ld + i] * G[j * ld + i];
+        s = wave_allsum(s);
+        if (lane == 0) s_sig[j] = sqrt(s);
+    }
+    __syncthreads();
+    mfma_rebuild<T, NT>(V, ld, s_sig, N, vs, us);
+    if (Vs)
+        for (int idx = tid; idx < N * N; idx += NT) {
+            const int j = idx / N, i = idx - (idx / N) * N;
+            Vs[j * N + i] = V[j * ld + i];
+        }
+    __syncthreads();
+}
+
+template <typename T, int NT, typename GP, typename VP>
+__device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ us, int N, T *__restrict__ Vs, bool warm, GP G,
+                              VP V, int ld, T *__restrict__ Tm, typename Lds<T>::type *s_sig, const EigScratch &sc,
+                              int max_sweeps, int gs = 16, int jblock = 0) {
+    const int tid = threadIdx.x;
+    if (N == 1) {
+        if (tid == 0) {
+            const T w = vs[0];
+            const T x = w > (T)0 ? w : (T)0;
+            us[0] = x;
+            vs[0] = x - w;
+            if (Vs) Vs[0] = (T)1;
+        }
+        __syncthreads();
+        return;
+    }
+    const double fro2 = stage_block<T, NT>(vs, N, Vs, warm, G, V, ld, Tm, sc);
     // a pair is rotated while it is coupled beyond rounding, relative to both columns
     // (16 eps) and absolutely (eps |W|_F times the larger column): below that, the pair's
     // contribution to |W| is under the rounding error of W itself, and columns of
     // near-zero eigenvalues stop trading noise
     const T tol = jacobi_tol<T>(sc.jtol);
     const T atol = (T)(jacobi_atol_factor(N) * TS<T>::eps * sqrt(fro2));
-    const int M = N + (N & 1);
-    const int H = M / 2;
     int nsw = 0;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         if (tid == 0) *sc.s_flag = 0;
@@ -941,43 +1086,7 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
         // big: some rotation of the sweep had relative coupling above sqrt(tol).  Without one
         // the sweep is the last: cyclic Jacobi converges quadratically, so what such a sweep
         // leaves is coupling of order tol, which the next sweep would not rotate
-        int big = 0;
-        constexpr bool kBothLds = std::is_same<GP, typename Lds<T>::type *>::value && std::is_same<VP, GP>::value;
-        // lanes per column pair: a tile choice per block-size bucket (autotuned), or the
-        // block-cyclic order (G and V in LDS)
-        if (kBothLds && jblock == 8) {
-            if constexpr (kBothLds) big = block_cyclic_sweep<T, NT>(G, V, ld, N, tol, atol);
-        } else if (gs == 8) {
-            const int grp = tid / 8;
-            for (int r = 0; r < M - 1; ++r) {
-                for (int kk = grp; kk < H; kk += NT / 8) {
-                    int p, q;
-                    rr_pair(r, kk, M, p, q);
-                    if (q < N && os_rotate_pair<T, 8, GP, VP>(G, ld, V, ld, N, p, q, tol, atol) == 2) big = 1;
-                }
-                __syncthreads();
-            }
-        } else if (gs == 32) {
-            const int grp = tid / 32;
-            for (int r = 0; r < M - 1; ++r) {
-                for (int kk = grp; kk < H; kk += NT / 32) {
-                    int p, q;
-                    rr_pair(r, kk, M, p, q);
-                    if (q < N && os_rotate_pair<T, 32, GP, VP>(G, ld, V, ld, N, p, q, tol, atol) == 2) big = 1;
-                }
-                __syncthreads();
-            }
-        } else {
-            const int grp = tid / 16;
-            for (int r = 0; r < M - 1; ++r) {
-                for (int kk = grp; kk < H; kk += NT / 16) {
-                    int p, q;
-                    rr_pair(r, kk, M, p, q);
-                    if (q < N && os_rotate_pair<T, 16, GP, VP>(G, ld, V, ld, N, p, q, tol, atol) == 2) big = 1;
-                }
-                __syncthreads();
-            }
-        }
+        const int big = sweep_block<T, NT>(G, V, ld, N, tol, atol, gs, jblock);
         if (big) *sc.s_flag = 1;
         __syncthreads();
         const int any = *sc.s_flag;
@@ -987,22 +1096,54 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
     }
     // counted after the loop: no thread-0 block ends the body next to the one that begins it
     if (tid == 0) *sc.s_sweeps += nsw;
-    // sigma_j = |g_j|
-    for (int j = wid; j < N; j += NW) {
-        T s = 0;
-        for (int i = lane; i < N; i += 64) s += G[j * ld + i] * G[j * ld + i];
-        s = wave_allsum(s);
-        if (lane == 0) s_sig[j] = sqrt(s);
-    }
-    __syncthreads();
-    // u = lower((W + V Sigma V^T) / 2), v = u - w, on the matrix cores
-    mfma_rebuild<T, NT>(V, ld, s_sig, N, vs, us);
-    if (Vs)
-        for (int idx = tid; idx < N * N; idx += NT) {
-            const int j = idx / N, i = idx - (idx / N) * N;
-            Vs[j * N + i] = V[j * ld + i];
+    finish_block<T, NT>(vs, us, N, Vs, G, V, ld, s_sig);
+}
+
+// Projects the two blocks of a problem together (both at least 2 x 2, G and V of both in LDS from
+// s_mat on, columns padded to lds_ld): each staged as project_block stages it, then sweeps of both
+// at once (block_cyclic_sweep2) until each has had a sweep without a rotation of relative coupling
+// above sqrt(tol) (or max_sweeps), each block's sweeps counted and stopped as project_block's, then
+// each finished as project_block finishes it.  Every block's arithmetic is the same as projecting
+// it alone; the smaller block's sweeps run on wavefronts the larger one leaves idle.
+template <typename T, int NT>
+__device__ __noinline__ void project_two(T *__restrict__ vs1, T *__restrict__ us1, int N1, T *__restrict__ Vs1,
+                                         T *__restrict__ vs2, T *__restrict__ us2, int N2, T *__restrict__ Vs2, bool warm,
+                                         typename Lds<T>::type *s_mat, T *__restrict__ Tm, typename Lds<T>::type *s_sig,
+                                         const EigScratch &sc, int max_sweeps) {
+    typedef typename Lds<T>::type *LP;
+    __shared__ int s_vote[2];
+    const int tid = threadIdx.x;
+    const int ld1 = lds_ld(N1), ld2 = lds_ld(N2);
+    LP G1 = s_mat, V1 = G1 + (long long)N1 * ld1, G2 = V1 + (long long)N1 * ld1, V2 = G2 + (long long)N2 * ld2;
+    const double fro1 = stage_block<T, NT>(vs1, N1, Vs1, warm, G1, V1, ld1, Tm, sc);
+    const double fro2 = stage_block<T, NT>(vs2, N2, Vs2, warm, G2, V2, ld2, Tm, sc);
+    const T tol = jacobi_tol<T>(sc.jtol);
+    const T atol1 = (T)(jacobi_atol_factor(N1) * TS<T>::eps * sqrt(fro1));
+    const T atol2 = (T)(jacobi_atol_factor(N2) * TS<T>::eps * sqrt(fro2));
+    bool act1 = true, act2 = true;
+    int nsw1 = 0, nsw2 = 0;
+    for (int sweep = 0; sweep < max_sweeps && (act1 || act2); ++sweep) {
+        if (tid == 0) s_vote[0] = s_vote[1] = 0;
+        __syncthreads();
+        int b1, b2;
+        block_cyclic_sweep2<T, NT, LP>(G1, V1, ld1, N1, tol, atol1, act1, G2, V2, ld2, N2, tol, atol2, act2, b1, b2);
+        if (b1) s_vote[0] = 1;
+        if (b2) s_vote[1] = 1;
+        __syncthreads();
+        const int any1 = s_vote[0], any2 = s_vote[1];
+        __syncthreads();
+        if (act1) {
+            ++nsw1;
+            if (!any1) act1 = false;
         }
-    __syncthreads();
+        if (act2) {
+            ++nsw2;
+            if (!any2) act2 = false;
+        }
+    }
+    if (tid == 0) *sc.s_sweeps += nsw1 + nsw2;
+    finish_block<T, NT>(vs1, us1, N1, Vs1, G1, V1, ld1, s_sig);
+    finish_block<T, NT>(vs2, us2, N2, Vs2, G2, V2, ld2, s_sig);
 }
 
 // ----------------------------------------------------------------------------- PSD projection, helpers
@@ -1465,7 +1606,22 @@ __device__ __noinline__ int run_phase(const ProbDesc &P, const RunParams &rp, ch
         const unsigned long long t1 = wall_clock64();
         t_aff += t1 - t0;
         long long voff = 0;
-        for (int bk = 0; bk < P.nblk; ++bk) {
+        // two blocks that both take the lane-group form with G and V in LDS, in the block-cyclic
+        // order, and fit in LDS together: projected at once
+        const bool two = P.nblk == 2 && rp.jac_block == 8 && rp.lds_pair > 0 && [&] {
+            for (int bk = 0; bk < 2; ++bk) {
+                const int N = P.blk_N[bk];
+                if (N < 2 || N > rp.lds_nmax || (N <= rp.rows_nmax && N >= rp.rows_nmin)) return false;
+            }
+            return sos_pair_need(P.blk_N[0], P.blk_N[1]) <= rp.lds_pair;
+        }();
+        if (two) {
+            const int N0 = P.blk_N[0], N1 = P.blk_N[1];
+            project_two<T, NT>(v + P.blk_off[0], u + P.blk_off[0], N0, rp.warm_eig ? vstore : nullptr, v + P.blk_off[1],
+                               u + P.blk_off[1], N1, rp.warm_eig ? vstore + (long long)N0 * N0 : nullptr,
+                               rp.warm_eig && warm, s_mat, Tm, s_sig, sc, rp.max_sweeps);
+        }
+        for (int bk = 0; bk < (two ? 0 : P.nblk); ++bk) {
             const int off = P.blk_off[bk];
             const int N = P.blk_N[bk];
             if (N <= rp.rows_nmax && N >= rp.rows_nmin) {
@@ -2527,12 +2683,25 @@ void lds_layout(int eig_ld, int lds_budget, int nw, int &mat_off, int &lds_nmax,
     if (need_z > bytes) bytes = need_z;
 }
 
+// LDS for projecting a two-block problem's blocks at once (project_two): enlarges the launch's
+// dynamic LDS to hold both blocks' G and V after the sigma area when the budget allows.
+template <typename T>
+void pair_layout(RunParams &rp, size_t &bytes) {
+    rp.lds_pair = 0;
+    if (rp.pair_need <= 0) return;
+    const size_t need = (size_t)rp.lds_mat_off + sizeof(T) * (size_t)rp.pair_need;
+    if (need > (size_t)rp.lds_budget) return;
+    rp.lds_pair = rp.pair_need;
+    if (need > bytes) bytes = need;
+}
+
 template <typename T, int NT>
 int launch_t(int grid, const RunParams &rp_in, hipStream_t st) {
     RunParams rp = rp_in;
     size_t lds = 0;
     lds_layout<T>(rp.eig_ld, rp.lds_budget, NT / 64, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds, rp.eig_wave,
                   rp.rows_nmax);
+    pair_layout<T>(rp, lds);
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&admm_persistent<T, NT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -2550,6 +2719,8 @@ int launch_mixed(int grid, const RunParams &rp32_in, const RunParams &rp64_in, h
                       rp32.eig_wave, rp32.rows_nmax);
     lds_layout<double>(rp64.eig_ld, rp64.lds_budget, NT / 64, rp64.lds_mat_off, rp64.lds_nmax, rp64.lds_nmax_g, lds64,
                        rp64.eig_wave, rp64.rows_nmax);
+    pair_layout<float>(rp32, lds32);
+    pair_layout<double>(rp64, lds64);
     const size_t lds = lds32 > lds64 ? lds32 : lds64;
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&admm_mixed<NT>),
