@@ -831,12 +831,15 @@ __device__ __forceinline__ int block_cyclic_sweep(LP G, LP V, int ld, int N, T t
     const int wid = threadIdx.x >> 6, grp = (threadIdx.x & 63) >> 3;
     const int nb = (N + 7) >> 3, nbp = nb + (nb & 1);
     int big = 0;
-    for (int B = wid; B < nb; B += NW) {
-        const int c0 = B * 8, c = N - c0 < 8 ? N - c0 : 8, M = c + (c & 1);
-        for (int r = 0; r < M - 1; ++r) {
-            if (grp < M / 2) {
+    // in-block pairs: a block has at most 4 disjoint pairs per round, so a wavefront takes two
+    // blocks at once, one per half (lane groups 0-3 and 4-7)
+    const int half = grp >> 2, hg = grp & 3;
+    for (int B = 2 * wid + half; B - half < nb; B += 2 * NW) {
+        const int c0 = B * 8, c = B < nb ? (N - c0 < 8 ? N - c0 : 8) : 0, M = c + (c & 1);
+        for (int r = 0; r < 7; ++r) {   // the rounds of a full block; shorter blocks idle
+            if (r < M - 1 && hg < M / 2) {
                 int p, q;
-                rr_pair(r, grp, M, p, q);
+                rr_pair(r, hg, M, p, q);
                 if (q < c && os_rotate_pair<T, 8, LP, LP>(G, ld, V, ld, N, c0 + p, c0 + q, tol, atol) == 2) big = 1;
             }
             wave_order();
@@ -880,17 +883,20 @@ __device__ __forceinline__ void block_cyclic_sweep2(LP G1, LP V1, int ld1, int N
     const int nb1 = act1 ? (N1 + 7) >> 3 : 0, nb2 = act2 ? (N2 + 7) >> 3 : 0;
     const int nbp1 = nb1 + (nb1 & 1), nbp2 = nb2 + (nb2 & 1);
     big1 = big2 = 0;
-    for (int Bk = wid; Bk < nb1 + nb2; Bk += NW) {
+    // in-block pairs: two blocks per wavefront, one per half (as in block_cyclic_sweep)
+    const int half = grp >> 2, hg = grp & 3;
+    for (int Bk = 2 * wid + half; Bk - half < nb1 + nb2; Bk += 2 * NW) {
         const bool one = Bk < nb1;
         LP G = one ? G1 : G2;
         LP V = one ? V1 : V2;
         const int ld = one ? ld1 : ld2, N = one ? N1 : N2;
         const T tol = one ? tol1 : tol2, atol = one ? atol1 : atol2;
-        const int c0 = (one ? Bk : Bk - nb1) * 8, c = N - c0 < 8 ? N - c0 : 8, M = c + (c & 1);
-        for (int r = 0; r < M - 1; ++r) {
-            if (grp < M / 2) {
+        const int c0 = (one ? Bk : Bk - nb1) * 8;
+        const int c = Bk < nb1 + nb2 ? (N - c0 < 8 ? N - c0 : 8) : 0, M = c + (c & 1);
+        for (int r = 0; r < 7; ++r) {   // the rounds of a full block; shorter blocks idle
+            if (r < M - 1 && hg < M / 2) {
                 int p, q;
-                rr_pair(r, grp, M, p, q);
+                rr_pair(r, hg, M, p, q);
                 if (q < c && os_rotate_pair<T, 8, LP, LP>(G, ld, V, ld, N, c0 + p, c0 + q, tol, atol) == 2) {
                     if (one) big1 = 1;
                     else big2 = 1;
