@@ -118,6 +118,7 @@ struct RunParams {
                             //    blocks need together (the largest over the problems; 0: none)
     int lds_pair;           // filled in by the launcher: pair_need if the launch's LDS holds it, else 0;
                             //    a two-block problem that fits projects both blocks at once
+    long long lds_bytes;    // filled in by the launcher: the launch's dynamic LDS bytes (0: unknown)
     unsigned long long *ts; // optional [start, end] wall-clock stamps of the launch (min / max over workgroups)
 };
 

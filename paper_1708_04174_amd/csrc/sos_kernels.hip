@@ -196,14 +196,20 @@ __device__ __forceinline__ T group_allsum(T x) {
 // T: storage type of u, v, A, b, c, h; AT: the type the affine step computes and
 // accumulates in (the storage type; a variant with FP64 arithmetic on FP32 storage
 // left the FP32 residual floor unchanged, since the floor comes from the stored iterate).
-template <typename T, int NT, typename AT>
-__device__ __noinline__ void affine_phase(const ProbDesc &P, const RunParams &rp, AT *__restrict__ wy, AT *__restrict__ wx,
-                             double *s_z, double *s_red) {
+template <typename T, int NT, typename AT, typename WP>
+__device__ __forceinline__ void affine_core(const ProbDesc &P, const RunParams &rp, WP wy, WP wx, WP w1s, double *s_z,
+                                            double *s_red) {
+    // WP an LDS pointer: w1 = u + v - c wt (the columns' part of the right-hand side) is staged
+    // once, and the work vectors x / sigma_2 (wy) and sigma_1 (wx) stay in LDS; else all global
+    constexpr bool kStaged = !std::is_same<WP, AT *>::value;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     constexpr int NW = NT / 64;
     const int m = P.m, nx = P.nx, k = P.k, nfree = P.nfree;
     // an A_f wider than the LDS k-vector: the k-vector and partial sums live past the work vectors
-    if (k > SOS_KMAX_LDS) s_z = reinterpret_cast<double *>(reinterpret_cast<char *>(wy) + sizeof(double) * ((long long)((m + 63) & ~63) + nx + 64));
+    // (the staged form is only taken with the k-vector in LDS)
+    if constexpr (!kStaged)
+        if (k > SOS_KMAX_LDS)
+            s_z = reinterpret_cast<double *>(reinterpret_cast<char *>(wy) + sizeof(double) * ((long long)((m + 63) & ~63) + nx + 64));
     T *__restrict__ u = TS<T>::u(P);
     T *__restrict__ v = TS<T>::v(P);
     const T *__restrict__ val = TS<T>::val(P);
@@ -223,6 +229,15 @@ __device__ __noinline__ void affine_phase(const ProbDesc &P, const RunParams &rp
     const double wtau = tau + kap;
     const AT wt = (AT)wtau;
     const T *__restrict__ uy = u + nx;
+    if constexpr (kStaged) {
+        for (int e = tid; e < nx; e += NT) w1s[e] = (AT)u[e] + (AT)v[e] - (AT)c[e] * wt;
+        __syncthreads();
+    }
+    // the column's part (u + v - c wt) at column j, staged or read
+    auto w1 = [&](int j) -> AT {
+        if constexpr (kStaged) return w1s[j];
+        else return (AT)u[j] + (AT)v[j] - (AT)c[j] * wt;
+    };
 
     // P1: x = (w2 - A w1) / d.  A row has up to a few tens of nonzeros, each a chain of two
     // dependent loads (column index, then u, v, c there): four entries in flight at a time
@@ -233,14 +248,14 @@ __device__ __noinline__ void affine_phase(const ProbDesc &P, const RunParams &rp
         int e = rowptr[a];
         for (; e + 4 <= e1; e += 4) {
             const int j0 = colidx[e], j1 = colidx[e + 1], j2 = colidx[e + 2], j3 = colidx[e + 3];
-            acc -= (AT)val[e] * ((AT)u[j0] + (AT)v[j0] - (AT)c[j0] * wt);
-            acc1 -= (AT)val[e + 1] * ((AT)u[j1] + (AT)v[j1] - (AT)c[j1] * wt);
-            acc2 -= (AT)val[e + 2] * ((AT)u[j2] + (AT)v[j2] - (AT)c[j2] * wt);
-            acc3 -= (AT)val[e + 3] * ((AT)u[j3] + (AT)v[j3] - (AT)c[j3] * wt);
+            acc -= (AT)val[e] * w1(j0);
+            acc1 -= (AT)val[e + 1] * w1(j1);
+            acc2 -= (AT)val[e + 2] * w1(j2);
+            acc3 -= (AT)val[e + 3] * w1(j3);
         }
         for (; e < e1; ++e) {
             const int j = colidx[e];
-            acc -= (AT)val[e] * ((AT)u[j] + (AT)v[j] - (AT)c[j] * wt);
+            acc -= (AT)val[e] * w1(j);
         }
         wy[a] = (acc + acc1 + (acc2 + acc3)) * (AT)dinv[a];
     }
@@ -298,8 +313,8 @@ __device__ __noinline__ void affine_phase(const ProbDesc &P, const RunParams &rp
         for (int e = tid; e < nx; e += NT) {
             const int r = colrow[e];
             if (r <= -2) continue;
-            const AT w1 = (AT)u[e] + (AT)v[e] - (AT)c[e] * wt;
-            const AT s1 = r >= 0 ? w1 + (AT)colval[e] * wy[r] : w1;
+            const AT we = w1(e);
+            const AT s1 = r >= 0 ? we + (AT)colval[e] * wy[r] : we;
             wx[e] = s1;
             cs += (double)cw[e] * (double)s1;
         }
@@ -314,7 +329,7 @@ __device__ __noinline__ void affine_phase(const ProbDesc &P, const RunParams &rp
             acc = group_allsum<8>(acc);
             if (gl == 0) {
                 const int e = fcol[j];
-                const AT s1 = (AT)u[e] + (AT)v[e] - (AT)c[e] * wt + acc;
+                const AT s1 = w1(e) + acc;
                 wx[e] = s1;
                 cs += (double)cw[e] * (double)s1;
             }
@@ -352,6 +367,23 @@ __device__ __noinline__ void affine_phase(const ProbDesc &P, const RunParams &rp
         P.tk[1] = tn - wtt;
     }
     __syncthreads();
+}
+
+// The affine step of one problem by the workgroup.  wy, wx: its global work vectors; lds: the
+// LDS area the eigensolver leaves free during the step (nullptr if none) and lds_cap its bytes.
+// When x / sigma_2 (m), sigma_1 (nx) and the staged column part (nx) fit there, they live in LDS
+// (the arithmetic is the same; only where the vectors live changes).
+template <typename T, int NT, typename AT>
+__device__ __noinline__ void affine_phase(const ProbDesc &P, const RunParams &rp, AT *__restrict__ wy, AT *__restrict__ wx,
+                                          double *s_z, double *s_red, char *lds = nullptr, long long lds_cap = 0) {
+    typedef typename Lds<AT>::type *LW;
+    const long long mp = (P.m + 3) & ~3LL, nxp = (P.nx + 3) & ~3LL;
+    if (lds && P.k <= SOS_KMAX_LDS && (long long)sizeof(AT) * (mp + 2 * nxp) <= lds_cap) {
+        LW l = as_lds<AT>(lds);
+        affine_core<T, NT, AT, LW>(P, rp, l, l + mp, l + mp + nxp, s_z, s_red);
+    } else {
+        affine_core<T, NT, AT, AT *>(P, rp, wy, wx, nullptr, s_z, s_red);
+    }
 }
 
 // ----------------------------------------------------------------------------- PSD projection
@@ -1580,6 +1612,9 @@ __device__ __noinline__ int run_phase(const ProbDesc &P, const RunParams &rp, ch
     typename Lds<T>::type *s_sig = as_lds<T>(dyn_lds);
     typename Lds<T>::type *s_mat = as_lds<T>(dyn_lds + rp.lds_mat_off);
     double *s_z = reinterpret_cast<double *>(dyn_lds + rp.lds_mat_off);
+    // the affine step's LDS past its k-vector and partial sums (2 SOS_KMAX_LDS doubles)
+    char *aff_lds = dyn_lds + rp.lds_mat_off + sizeof(double) * 2 * SOS_KMAX_LDS;
+    const long long aff_cap = (long long)rp.lds_bytes - rp.lds_mat_off - (long long)sizeof(double) * 2 * SOS_KMAX_LDS;
     double *s_red = sc.s_red;
     T *wy = reinterpret_cast<T *>(wbase);
     T *wx = wy + ((P.m + 63) & ~63);
@@ -1608,7 +1643,7 @@ __device__ __noinline__ int run_phase(const ProbDesc &P, const RunParams &rp, ch
     bool stalled = false;
     while (it < cap) {
         t0 = wall_clock64();
-        affine_phase<T, NT, T>(P, rp, wy, wx, s_z, s_red);
+        affine_phase<T, NT, T>(P, rp, wy, wx, s_z, s_red, aff_lds, aff_cap);
         const unsigned long long t1 = wall_clock64();
         t_aff += t1 - t0;
         long long voff = 0;
@@ -2708,6 +2743,7 @@ int launch_t(int grid, const RunParams &rp_in, hipStream_t st) {
     lds_layout<T>(rp.eig_ld, rp.lds_budget, NT / 64, rp.lds_mat_off, rp.lds_nmax, rp.lds_nmax_g, lds, rp.eig_wave,
                   rp.rows_nmax);
     pair_layout<T>(rp, lds);
+    rp.lds_bytes = (long long)lds;
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&admm_persistent<T, NT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -2728,6 +2764,7 @@ int launch_mixed(int grid, const RunParams &rp32_in, const RunParams &rp64_in, h
     pair_layout<float>(rp32, lds32);
     pair_layout<double>(rp64, lds64);
     const size_t lds = lds32 > lds64 ? lds32 : lds64;
+    rp32.lds_bytes = rp64.lds_bytes = (long long)lds;   // one allocation serves both phases
     if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&admm_mixed<NT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
