@@ -125,14 +125,14 @@ struct RunParams {
 // Leading dimension of an N x N eigensolver matrix in LDS: columns padded to 8 mod 16 elements,
 // so that a wavefront's reads of a round's columns fall in distinct banks.
 #define SOS_LDS_LD(N) ((N) <= 8 ? (N) : ((((N) + 7) & ~15) + 8))
-// LDS elements that G and V of two blocks N1, N2 take together (0 unless both are at least 2);
-// host and device code share it
+// LDS elements that G and V of two blocks N1, N2 take together, and block 2's sigma (0 unless both
+// are at least 2); host and device code share it
 #if defined(__HIP__)
 __host__ __device__
 #endif
 static inline long long sos_pair_need(int N1, int N2) {
     if (N1 < 2 || N2 < 2) return 0;
-    return 2LL * ((long long)N1 * SOS_LDS_LD(N1) + (long long)N2 * SOS_LDS_LD(N2));
+    return 2LL * ((long long)N1 * SOS_LDS_LD(N1) + (long long)N2 * SOS_LDS_LD(N2)) + N2;
 }
 
 // Control block of a cooperative (multi-workgroup) launch on one problem, in device memory.

@@ -1137,6 +1137,126 @@ __device__ __noinline__ void project_block(T *__restrict__ vs, T *__restrict__ u
     finish_block<T, NT>(vs, us, N, Vs, G, V, ld, s_sig);
 }
 
+// stage_block for two blocks at once (project_two): one staging pass over both blocks' entries,
+// one pass of warm products over both blocks' 16 x 16 tiles (each wavefront holding its tiles of
+// both until every read of W is done), so the smaller block fills slots the larger leaves idle.
+// Falls back to two stage_block calls when a wavefront would hold more than kMfmaHold tiles.
+// Returns |W_1|_F^2 and |W_2|_F^2 (every thread).
+template <typename T, int NT, typename LP>
+__device__ __forceinline__ void stage_pair(T *__restrict__ vs1, int N1, T *__restrict__ Vs1, LP G1, LP V1, int ld1,
+                                           T *__restrict__ vs2, int N2, T *__restrict__ Vs2, LP G2, LP V2, int ld2,
+                                           bool warm, T *__restrict__ Tm, const EigScratch &sc, double &fro1,
+                                           double &fro2) {
+    typedef typename Mma<T>::acc AC;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr int NW = NT / 64;
+    const int nt1 = (N1 + 15) >> 4, nt2 = (N2 + 15) >> 4;
+    const int ntt1 = nt1 * nt1, ntt2 = nt2 * nt2;
+    if (warm && ntt1 + ntt2 > NW * kMfmaHold) {
+        fro1 = stage_block<T, NT>(vs1, N1, Vs1, warm, G1, V1, ld1, Tm, sc);
+        fro2 = stage_block<T, NT>(vs2, N2, Vs2, warm, G2, V2, ld2, Tm, sc);
+        return;
+    }
+    double f1 = 0.0, f2 = 0.0;
+    const int e1 = N1 * N1, etot = e1 + N2 * N2;
+    for (int idx = tid; idx < etot; idx += NT) {
+        const bool one = idx < e1;
+        const int N = one ? N1 : N2, ld = one ? ld1 : ld2, id = one ? idx : idx - e1;
+        const int j = id / N, i = id - j * N;
+        const int a = i > j ? i : j, bb = i > j ? j : i;
+        const T x = (one ? vs1 : vs2)[svec_idx(a, bb, N)];
+        const T vv = warm ? (one ? Vs1 : Vs2)[j * N + i] : (i == j ? (T)1 : (T)0);
+        (one ? G1 : G2)[j * ld + i] = x;   // W where G goes (warm: read back by the products below)
+        (one ? V1 : V2)[j * ld + i] = vv;
+        if (one) f1 += (double)x * (double)x;
+        else f2 += (double)x * (double)x;
+    }
+    __syncthreads();
+    if (warm) {
+        // G = W V_prev: tile c of the combined list (block 1's ntt1 tiles, then block 2's) to
+        // wavefront c mod NW, W read from G's storage, written after the barrier
+        const int li = lane & 15, lg = lane >> 4;
+        AC acc[kMfmaHold];
+#pragma unroll
+        for (int q = 0; q < kMfmaHold; ++q) {
+            acc[q] = (AC)(T)0;
+            const int c = q * NW + wid;
+            if (c >= ntt1 + ntt2) continue;
+            const bool one = c < ntt1;
+            const int nt = one ? nt1 : nt2, tl = one ? c : c - ntt1, N = one ? N1 : N2, ld = one ? ld1 : ld2;
+            LP W = one ? G1 : G2;
+            LP V = one ? V1 : V2;
+            const int i = (tl % nt) * 16 + li, j = (tl / nt) * 16 + li;
+            const bool iok = i < N, jok = j < N;
+            for (int k0 = 0; k0 < N; k0 += 16) {
+                const int kb = k0 + 4 * lg;
+                T a[4], b[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const bool kok = kb + t < N;
+                    a[t] = (iok && kok) ? W[(long long)i * ld + kb + t] : (T)0;
+                    b[t] = (jok && kok) ? V[(long long)j * ld + kb + t] : (T)0;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[q] = Mma<T>::step(a[t], b[t], acc[q]);
+            }
+        }
+        __syncthreads();   // every read of W done before G, its storage, is written
+#pragma unroll
+        for (int q = 0; q < kMfmaHold; ++q) {
+            const int c = q * NW + wid;
+            if (c >= ntt1 + ntt2) continue;
+            const bool one = c < ntt1;
+            const int nt = one ? nt1 : nt2, tl = one ? c : c - ntt1, N = one ? N1 : N2, ld = one ? ld1 : ld2;
+            LP G = one ? G1 : G2;
+            const int i0 = (tl % nt) * 16, j = (tl / nt) * 16 + li;
+            if (j >= N) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + Mma<T>::row(lg, r);
+                if (i < N) G[(long long)j * ld + i] = acc[q][r];
+            }
+        }
+        __syncthreads();
+    }
+    block_sum2<NT>(f1, f2, sc.s_red);
+    fro1 = f1;
+    fro2 = f2;
+}
+
+// finish_block for two blocks at once: both blocks' sigma in one pass (block 2's after its V), the
+// two rebuilds' tiles spread as one list over the wavefronts, both caches written, one barrier.
+template <typename T, int NT, typename LP>
+__device__ __forceinline__ void finish_pair(T *__restrict__ vs1, T *__restrict__ us1, int N1, T *__restrict__ Vs1, LP G1,
+                                            LP V1, int ld1, LP sig1, T *__restrict__ vs2, T *__restrict__ us2, int N2,
+                                            T *__restrict__ Vs2, LP G2, LP V2, int ld2, LP sig2) {
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr int NW = NT / 64;
+    for (int c = wid; c < N1 + N2; c += NW) {
+        const bool one = c < N1;
+        const int j = one ? c : c - N1, ld = one ? ld1 : ld2, N = one ? N1 : N2;
+        LP G = one ? G1 : G2;
+        T sum = 0;
+        for (int i = lane; i < N; i += 64) sum += G[j * ld + i] * G[j * ld + i];
+        sum = wave_allsum(sum);
+        if (lane == 0) (one ? sig1 : sig2)[j] = sqrt(sum);
+    }
+    __syncthreads();
+    const int nt1 = (N1 + 15) >> 4, ntri1 = nt1 * (nt1 + 1) / 2;
+    mfma_rebuild<T, NT>(V1, ld1, sig1, N1, vs1, us1, wid, NW);
+    mfma_rebuild<T, NT>(V2, ld2, sig2, N2, vs2, us2, ((wid - ntri1) % NW + NW) % NW, NW);
+    const int e1 = N1 * N1, etot = e1 + N2 * N2;
+    for (int idx = tid; idx < etot; idx += NT) {
+        const bool one = idx < e1;
+        T *Vs = one ? Vs1 : Vs2;
+        if (!Vs) continue;
+        const int N = one ? N1 : N2, ld = one ? ld1 : ld2, id = one ? idx : idx - e1;
+        const int j = id / N, i = id - j * N;
+        Vs[j * N + i] = (one ? V1 : V2)[j * ld + i];
+    }
+    __syncthreads();
+}
+
 // Projects the two blocks of a problem together (both at least 2 x 2, G and V of both in LDS from
 // s_mat on, columns padded to lds_ld): each staged as project_block stages it, then sweeps of both
 // at once (block_cyclic_sweep2) until each has had a sweep without a rotation of relative coupling
@@ -1153,8 +1273,9 @@ __device__ __noinline__ void project_two(T *__restrict__ vs1, T *__restrict__ us
     const int tid = threadIdx.x;
     const int ld1 = lds_ld(N1), ld2 = lds_ld(N2);
     LP G1 = s_mat, V1 = G1 + (long long)N1 * ld1, G2 = V1 + (long long)N1 * ld1, V2 = G2 + (long long)N2 * ld2;
-    const double fro1 = stage_block<T, NT>(vs1, N1, Vs1, warm, G1, V1, ld1, Tm, sc);
-    const double fro2 = stage_block<T, NT>(vs2, N2, Vs2, warm, G2, V2, ld2, Tm, sc);
+    LP sig2 = V2 + (long long)N2 * ld2;   // block 2's sigma (s_sig holds block 1's)
+    double fro1, fro2;
+    stage_pair<T, NT, LP>(vs1, N1, Vs1, G1, V1, ld1, vs2, N2, Vs2, G2, V2, ld2, warm, Tm, sc, fro1, fro2);
     const T tol = jacobi_tol<T>(sc.jtol);
     const T atol1 = (T)(jacobi_atol_factor(N1) * TS<T>::eps * sqrt(fro1));
     const T atol2 = (T)(jacobi_atol_factor(N2) * TS<T>::eps * sqrt(fro2));
@@ -1180,8 +1301,7 @@ __device__ __noinline__ void project_two(T *__restrict__ vs1, T *__restrict__ us
         }
     }
     if (tid == 0) *sc.s_sweeps += nsw1 + nsw2;
-    finish_block<T, NT>(vs1, us1, N1, Vs1, G1, V1, ld1, s_sig);
-    finish_block<T, NT>(vs2, us2, N2, Vs2, G2, V2, ld2, s_sig);
+    finish_pair<T, NT, LP>(vs1, us1, N1, Vs1, G1, V1, ld1, s_sig, vs2, us2, N2, Vs2, G2, V2, ld2, sig2);
 }
 
 // ----------------------------------------------------------------------------- PSD projection, helpers
