@@ -218,7 +218,7 @@ def table2(ns, tol: float, seed: int = 0):
     return out
 
 
-def per_iteration(cases, warm_iters: int, timed_iters: int):
+def per_iteration(cases, warm_iters: int, timed_iters: int, eig_form: int = 0):
     """ms per iteration of sos_step on single problems (one workgroup), after warm_iters
     iterations (warm Jacobi starts settled), in both precision forms, with the device-clock
     split by phase and the mean Jacobi sweeps per block."""
@@ -229,7 +229,7 @@ def per_iteration(cases, warm_iters: int, timed_iters: int):
         gen, desc = PER_ITER_CASES[name]
         prob = gen(F)
         for prec, pname in ((B.SOS_FP32_MIXED, "fp32"), (B.SOS_FP64, "fp64")):
-            w = B.setup_problem(prob, B.sos_default_settings(precision=prec))
+            w = B.setup_problem(prob, B.sos_default_settings(precision=prec, eig_form=eig_form))
             B.sos_step(w, warm_iters)
             inf = B.sos_step(w, timed_iters)
             w.free()
@@ -320,6 +320,9 @@ def main():
     ap.add_argument("--per-iter", nargs="*", default=None, metavar="CASE",
                     help="only time sos_step per iteration on single problems (cases: "
                          + ", ".join(PER_ITER_CASES) + "; none given: all) and print them as one JSON line")
+    ap.add_argument("--eig-form", type=int, default=0,
+                    help="--per-iter only: the eigensolver form of the single solves (sos_settings.eig_form; "
+                         "0 = the library's choice, 2 = one workgroup for every block)")
     ap.add_argument("--table2", nargs="*", type=int, default=None, metavar="N",
                     help="only solve Table II's local Lyapunov programs at these n (default: Table II's sizes) "
                          "in FP64 at --tol and print them as one JSON line")
@@ -356,7 +359,7 @@ def main():
         return
     if args.per_iter is not None:
         cases = args.per_iter or list(PER_ITER_CASES)
-        print(json.dumps({"per_iteration": per_iteration(cases, 100, 50)}), flush=True)
+        print(json.dumps({"per_iteration": per_iteration(cases, 100, 50, args.eig_form)}), flush=True)
         return
     from paper_1708_04174_amd import binding as B
     from paper_1708_04174_amd import warmstart as W
