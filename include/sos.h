@@ -94,8 +94,8 @@ typedef struct {
     int32_t partition;       /* SOS_PART_PAPER | SOS_PART_COLUMNS */
     int32_t block_threads;   /* threads per workgroup: 0 = default (512), else 64..1024, multiple of 64 */
     int32_t eig_form;        /* eigensolver of sos_step / sos_solve: 0 = library default (the
-                                lane-group form for N < 96, 8 lanes per column pair for N >= 64,
-                                the rows-over-wavefronts form from N = 96 for blocks that fit in
+                                lane-group form for N < 128, 8 lanes per column pair for N >= 64,
+                                the rows-over-wavefronts form from N = 128 for blocks that fit in
                                 LDS), 1 = rows form for every block that fits in LDS, 2 = lane-group
                                 form for every block, 3 = the multi-workgroup form for every block.
                                 In SOS_FP64, eig_form 0 also runs a single problem whose largest

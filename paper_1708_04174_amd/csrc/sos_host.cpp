@@ -23,10 +23,12 @@ thread_local std::string g_setup_error;
 // dynamic LDS a solver launch may take (gfx950: 160 KiB per workgroup, minus the static part)
 const int kLdsBudget = 159 * 1024;   // of the 160 KiB per workgroup, the rest for static LDS
 // Default eigensolver choice (single solves and schedules without these keys): the lane-group
-// form below N = 96, where it measured faster in both precisions, and the rows-over-wavefronts
-// form from 96 on for blocks that fit in LDS; lanes per column pair by block-size bucket
-// (N < 32, 64, 96, 128, 192, 256, larger): 8 for 64 <= N < 128, as the autotuner picks there.
-constexpr int kRowsNmin = 96;
+// form below N = 128 (with G and V in LDS, the block-cyclic order: at N = 120 0.41 against 0.65
+// ms per FP32 iteration for the rows form, even in FP64), and the rows-over-wavefronts form from
+// 128 on for blocks that fit in LDS (even with the lane-group form there); lanes per column pair
+// by block-size bucket (N < 32, 64, 96, 128, 192, 256, larger): 8 for 64 <= N < 128, as the
+// autotuner picks there.
+constexpr int kRowsNmin = 128;
 // Jacobi coupling tolerance of the mixed form's FP64 phase (0: 16 eps of FP64).  That phase
 // has to carry the iterate below the FP32 floor of the affine step and of the residuals; its
 // stopping test and certificates are evaluated in FP64 on the iterate itself, whatever the
