@@ -848,8 +848,8 @@ __device__ __forceinline__ int cross_block_regs(LP G, LP V, int ld, int N, int P
 }
 
 // Block-cyclic sweep of the lane-group form (G and V in LDS): the columns form blocks of 8;
-// first every block's own pairs (a wavefront per block, four 8-lane groups per round of the
-// block's round-robin), then block rounds over pairs of blocks (round-robin of the blocks), a
+// first every block's own pairs (two blocks per wavefront, four 8-lane groups each per round of
+// the block's round-robin), then block rounds over pairs of blocks (round-robin of the blocks), a
 // wavefront per block pair covering its 64 cross pairs in 8 steps of 8 disjoint pairs (group g
 // rotates columns 8P + g and 8Q + (g + s) mod 8 in step s).  Every column pair meets once per
 // sweep, as in the cyclic order, but only the block rounds end in a workgroup barrier (N / 8 + 1
