@@ -120,6 +120,9 @@ FP32_CASES = {
     "lyapunov_c5_seed3610": lambda: F.FAMILIES["c5"](3610),
     "pop_n10": lambda: F.pop_unconstrained(10, 3),
     "ball_c3_full": lambda: F.FAMILIES["c3"](0),
+    # blocks 105 and 14 fit in LDS together in FP32: the two-block projection with the larger
+    # block's cross rounds on the LDS steps (past N = 96)
+    "ball_n13_two_blocks": lambda: F.pop_ball(13, 0),
 }
 
 
