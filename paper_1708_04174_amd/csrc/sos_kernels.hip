@@ -753,18 +753,38 @@ __device__ __forceinline__ void mfma_rebuild(VP V, int ldv, SP sig, int N, T *__
 // the same wavefront) returns the written value without waiting for the write to finish.
 __device__ __forceinline__ void wave_order() { __builtin_amdgcn_wave_barrier(); }
 
-// Lane rotation by one 8-lane group across the wavefront: lane l takes lane (l + 8) mod 64.
-__device__ __forceinline__ float next_group(float x) { return __shfl(x, (int)((threadIdx.x + 8) & 63), 64); }
-__device__ __forceinline__ double next_group(double x) { return __shfl(x, (int)((threadIdx.x + 8) & 63), 64); }
+// Exchange between the 8-lane groups g and g ^ B of a wavefront (lane l takes lane l ^ 8B): for
+// B = 1 inside each row of 16 lanes, a DPP move (row_ror:8 swaps the row's halves) with no LDS
+// traffic; for B = 2 and 4 across rows, an LDS permute.  (The gfx950 permlane swaps in place of
+// the permutes measured slower.)
+template <int B>
+__device__ __forceinline__ unsigned group_xchg(unsigned x) {
+    static_assert(B == 1 || B == 2 || B == 4, "groups g and g ^ B");
+    if constexpr (B == 1) return (unsigned)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, true);
+    else return (unsigned)__shfl_xor((int)x, 8 * B, 64);
+}
+template <int B>
+__device__ __forceinline__ float group_xchg(float x) {
+    return __uint_as_float(group_xchg<B>(__float_as_uint(x)));
+}
+template <int B>
+__device__ __forceinline__ double group_xchg(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = group_xchg<B>((unsigned)u), hi = group_xchg<B>((unsigned)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 // The 64 cross pairs of blocks P and Q (8 columns each) by one wavefront, columns in registers:
-// group g keeps column 8P + g of G and V (RPL rows per lane) for the whole round and starts with
-// column 8Q + g; after each step every group passes its column of Q to the group before it (lane
-// l takes lane l + 8, wrapping), so in step s group g holds column 8Q + (g + s) mod 8, and after
-// the last step column 8Q + (g + 7) mod 8, which it writes back.  With VQ the V column of Q travels
+// group g keeps column 8P + g of G and V (RPL rows per lane) for the whole round; in step s it
+// holds column 8Q + (g ^ gray(s)) of Q, gray(s) = s ^ (s >> 1) (0, 1, 3, 2, 6, 7, 5, 4: every
+// column of Q once, and the groups' columns distinct in every step).  Consecutive Gray codes
+// differ in one bit, so between steps each group exchanges its column of Q with the group
+// g ^ 1 (four of the seven hand-overs, DPP moves inside rows of 16 lanes), g ^ 2 or g ^ 4 (LDS
+// permutes); after the last step group g writes back column 8Q + (g ^ 4).  The 8 steps are
+// unrolled, so each hand-over's kind is fixed at compile time.  With VQ the V column of Q travels
 // the same way; without, it stays in LDS and only a step that rotates reads and writes it (the
 // group that owns it next is in the same wavefront, whose LDS accesses are performed in order):
-// fewer shuffles when few pairs rotate, LDS traffic when many do.  Columns and rows at or past N
+// fewer lane moves when few pairs rotate, LDS traffic when many do.  Columns and rows at or past N
 // are zero (their products vanish; such columns are never rotated).  Returns 1 if a rotation had
 // relative coupling above sqrt(tol).
 template <typename T, int RPL, bool VQ, typename LP>
@@ -785,7 +805,7 @@ __device__ __forceinline__ int cross_block_regs(LP G, LP V, int ld, int N, int P
     }
     int big = 0;
     const T tol2 = tol * tol, atol2 = atol * atol;
-#pragma unroll 1
+#pragma unroll
     for (int st = 0; st < 8; ++st) {
         T al = 0, be = 0, ga = 0;
 #pragma unroll
@@ -800,7 +820,7 @@ __device__ __forceinline__ int cross_block_regs(LP G, LP V, int ld, int N, int P
         T cc, ss;
         if (jacobi_rot<T>(al, be, ga, tol2, atol2, cc, ss)) {   // then both columns are nonzero, so below N
             if (ga * ga > tol * (al * be)) big = 1;
-            const long long qo = (long long)(Q * 8 + ((grp + st) & 7)) * ld;
+            const long long qo = (long long)(Q * 8 + (grp ^ st ^ (st >> 1))) * ld;
 #pragma unroll
             for (int t = 0; t < RPL; ++t) {
                 const T a = xp[t], b = xq[t];
@@ -821,15 +841,23 @@ __device__ __forceinline__ int cross_block_regs(LP G, LP V, int ld, int N, int P
             }
         }
         wave_order();
-        if (st < 7) {
+        // gray(st) ^ gray(st + 1), the lowest set bit of st + 1 (none after the last step)
+        const int bit = (st + 1) & -(st + 1);
 #pragma unroll
-            for (int t = 0; t < RPL; ++t) {
-                xq[t] = next_group(xq[t]);
-                if constexpr (VQ) yq[t] = next_group(yq[t]);
+        for (int t = 0; t < RPL; ++t) {
+            if (bit == 1) {
+                xq[t] = group_xchg<1>(xq[t]);
+                if constexpr (VQ) yq[t] = group_xchg<1>(yq[t]);
+            } else if (bit == 2) {
+                xq[t] = group_xchg<2>(xq[t]);
+                if constexpr (VQ) yq[t] = group_xchg<2>(yq[t]);
+            } else if (bit == 4) {
+                xq[t] = group_xchg<4>(xq[t]);
+                if constexpr (VQ) yq[t] = group_xchg<4>(yq[t]);
             }
         }
     }
-    const int ql = Q * 8 + ((grp + 7) & 7);
+    const int ql = Q * 8 + (grp ^ 4);
 #pragma unroll
     for (int t = 0; t < RPL; ++t) {
         const int i = gl + 8 * t;
@@ -851,7 +879,8 @@ __device__ __forceinline__ int cross_block_regs(LP G, LP V, int ld, int N, int P
 // first every block's own pairs (two blocks per wavefront, four 8-lane groups each per round of
 // the block's round-robin), then block rounds over pairs of blocks (round-robin of the blocks), a
 // wavefront per block pair covering its 64 cross pairs in 8 steps of 8 disjoint pairs (group g
-// rotates columns 8P + g and 8Q + (g + s) mod 8 in step s).  Every column pair meets once per
+// rotates columns 8P + g and 8Q + (g + s) mod 8 in step s, or 8Q + (g ^ gray(s)) in the register
+// rounds).  Every column pair meets once per
 // sweep, as in the cyclic order, but only the block rounds end in a workgroup barrier (N / 8 + 1
 // per sweep instead of N - 1): inside a block round the wavefront's own LDS order suffices.
 // Up to N = 96 a cross round keeps its columns in registers (cross_block_regs): G and V up to
