@@ -73,6 +73,8 @@ SMALL = {
     "example_pop_n4": lambda: F.example_pop(4),
     "lyapunov_n2": lambda: F.lyapunov_from_field(2, F.lyapunov_field(2, np.random.default_rng(4))[2]),
     "lyapunov_c5_seed0": lambda: F.FAMILIES["c5"](0),
+    # N = 55: seven column blocks, the last one partial, in the register rounds of 33 <= N <= 64
+    "pop_n9": lambda: F.pop_unconstrained(9, 1),
 }
 
 
@@ -118,6 +120,7 @@ FP32_CASES = {
     "ball_n3_weighted": lambda: F.pop_ball(3, 2),
     "lyapunov_c5_seed0": lambda: F.FAMILIES["c5"](0),
     "lyapunov_c5_seed3610": lambda: F.FAMILIES["c5"](3610),
+    "pop_n9": lambda: F.pop_unconstrained(9, 1),
     "pop_n10": lambda: F.pop_unconstrained(10, 3),
     "ball_c3_full": lambda: F.FAMILIES["c3"](0),
     # blocks 105 and 14 fit in LDS together in FP32: the two-block projection with the larger
