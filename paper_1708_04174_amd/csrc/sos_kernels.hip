@@ -883,8 +883,8 @@ __device__ __forceinline__ int cross_block_regs(LP G, LP V, int ld, int N, int P
 // rounds).  Every column pair meets once per
 // sweep, as in the cyclic order, but only the block rounds end in a workgroup barrier (N / 8 + 1
 // per sweep instead of N - 1): inside a block round the wavefront's own LDS order suffices.
-// Up to N = 96 a cross round keeps its columns in registers (cross_block_regs): G and V up to
-// N = 32, G alone above; from N = 97 on the LDS steps measured as fast or faster.
+// Up to N = 128 a cross round keeps its columns in registers (cross_block_regs, 4 to 16 rows per
+// lane): G and V up to N = 32, G alone above; larger blocks take the LDS steps.
 // Returns 1 if some rotation had relative coupling above sqrt(tol).
 template <typename T, int NT, typename LP>
 __device__ __forceinline__ int block_cyclic_sweep(LP G, LP V, int ld, int N, T tol, T atol) {
@@ -912,10 +912,11 @@ __device__ __forceinline__ int block_cyclic_sweep(LP G, LP V, int ld, int N, T t
             int P, Q;
             rr_pair(R, pk, nbp, P, Q);
             if (Q >= nb) continue;
-            if (N <= 96) {
+            if (N <= 128) {
                 if (N <= 32) big |= cross_block_regs<T, 4, true>(G, V, ld, N, P, Q, tol, atol);
                 else if (N <= 64) big |= cross_block_regs<T, 8, false>(G, V, ld, N, P, Q, tol, atol);
-                else big |= cross_block_regs<T, 12, false>(G, V, ld, N, P, Q, tol, atol);
+                else if (N <= 96) big |= cross_block_regs<T, 12, false>(G, V, ld, N, P, Q, tol, atol);
+                else big |= cross_block_regs<T, 16, false>(G, V, ld, N, P, Q, tol, atol);
                 continue;
             }
             for (int st = 0; st < 8; ++st) {
@@ -985,6 +986,7 @@ __device__ __forceinline__ void block_cyclic_sweep2(LP G1, LP V1, int ld1, int N
             if (N <= 32) b = cross_block_regs<T, 4, true>(G, V, ld, N, P, Q, tol, atol);
             else if (N <= 64) b = cross_block_regs<T, 8, false>(G, V, ld, N, P, Q, tol, atol);
             else if (N <= 96) b = cross_block_regs<T, 12, false>(G, V, ld, N, P, Q, tol, atol);
+            else if (N <= 128) b = cross_block_regs<T, 16, false>(G, V, ld, N, P, Q, tol, atol);
             else
                 for (int st = 0; st < 8; ++st) {
                     const int p = P * 8 + grp, q = Q * 8 + ((grp + st) & 7);

@@ -122,6 +122,8 @@ FP32_CASES = {
     "lyapunov_c5_seed3610": lambda: F.FAMILIES["c5"](3610),
     "pop_n9": lambda: F.pop_unconstrained(9, 1),
     "pop_n10": lambda: F.pop_unconstrained(10, 3),
+    # N = 120: fifteen column blocks in the register rounds of 97 <= N <= 128
+    "pop_n14": lambda: F.pop_unconstrained(14, 0),
     "ball_c3_full": lambda: F.FAMILIES["c3"](0),
     # blocks 105 and 14 fit in LDS together in FP32: the two-block projection with the larger
     # block's cross rounds on the LDS steps (past N = 96)
