@@ -98,7 +98,7 @@ def test_step_parity_launch_shapes(B, threads):
 @pytest.mark.parametrize("form", [0, 1, 2])
 @pytest.mark.parametrize("case", ["c5", "pop_n14"])
 def test_step_parity_eigensolver_forms(B, form, case):
-    # single solves: default split at N = 96, rows form for every block, lane groups for every
+    # single solves: default split at N = 128, rows form for every block, lane groups for every
     # block; blocks of 28, 84 (Lyapunov) and 120 (quartic POP, n = 14)
     prob = F.FAMILIES["c5"](1) if case == "c5" else F.pop_unconstrained(14, 0)
     s = B.sos_default_settings(eig_form=form)
@@ -126,7 +126,7 @@ FP32_CASES = {
     "pop_n14": lambda: F.pop_unconstrained(14, 0),
     "ball_c3_full": lambda: F.FAMILIES["c3"](0),
     # blocks 105 and 14 fit in LDS together in FP32: the two-block projection with the larger
-    # block's cross rounds on the LDS steps (past N = 96)
+    # block's cross rounds at 16 rows per lane (97 <= N <= 128)
     "ball_n13_two_blocks": lambda: F.pop_ball(13, 0),
 }
 
