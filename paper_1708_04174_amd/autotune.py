@@ -6,7 +6,8 @@ a fixed number of iterations) and picks
      share one Jacobi column pair (8, 16 or 32) in the lane-group form of the
      eigensolver (blocks too large for the LDS form);
   2. for the whole batch: the eigensolver form for blocks that fit in LDS (rows split
-     over the wavefronts, or lane groups throughout), threads per workgroup and
+     over the wavefronts for every block or from N = 128 on, or lane groups throughout),
+     threads per workgroup and
      resident workgroups per CU (which also sets the LDS each workgroup may use).
 Writes the schedule JSON that sos_batch_setup reads.
 
@@ -92,8 +93,9 @@ def tune(probs, precision: int = 0, iters: int = 40, sample: int = 64, log=print
     works = _fixed_length_works([probs[i] for i in pick], iters)
     res = {}
     # eigensolver forms: (eig_wave, rows_nmin) = rows form for every block that fits in LDS,
-    # rows form from N = 96 on (lane groups below), lane groups for every block
-    for ew, rmin in ((2, 0), (2, 96), (0, 0)):
+    # rows form from N = 128 on (lane groups below: the single-solve default), lane groups for
+    # every block
+    for ew, rmin in ((2, 0), (2, 128), (0, 0)):
         for thr in (256, 512):
             for wpc in (1, 2):
                 s = dict(sched)
